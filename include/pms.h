@@ -1,0 +1,159 @@
+/*
+ * pms.h -- exact (l,d) planted motif search (PMS8) on one MI355X (gfx950).
+ *
+ * The problem (Section 1 of Nicolae & Rajasekaran, "Efficient Sequential and
+ * Parallel Algorithms for Planted Motif Search"): given n strings S_1..S_n of
+ * length m over an alphabet and integers l, d, report every l-mer M such that
+ * every S_i has a window S_i[j..j+l-1] with Hamming distance Hd(M, window) <= d.
+ * The result is a set; this library returns it sorted byte-lexicographically
+ * with no repeats.
+ *
+ * Every call below runs the whole method on the GPU: 2-bit l-mer packing,
+ * the all-pairs Hd <= 2d compatibility bit-matrix (Section 2.1), the
+ * sample-driven search over one l-mer per string with per-string survivor
+ * filtering by the pair condition and Theorem 1 (Section 2, Section 2.4,
+ * Algorithm 2), the pruned common d-neighbourhood generation (Algorithm 1),
+ * the candidate check against every remaining string, and sort/unique.
+ *
+ * Conventions
+ *  - Every function returns PMS_OK (0) or a negative pms_status.
+ *  - Strings are NUL-terminated and must have exactly m characters.
+ *  - The alphabet must have exactly 4 distinct characters on the GPU path
+ *    (DNA: "ACGT"); characters are case-sensitive.  Codes are assigned in
+ *    ascending ASCII order, so the result order is byte order of the motifs.
+ *  - Limits of the GPU path: 1 <= l <= 64, 0 <= d < l, 1 <= n <= 32,
+ *    m - l + 1 <= 2048.  m < l is valid and yields the empty set.
+ *  - Inputs are caller-owned and read only during the call (create/submit
+ *    copy them).  Results are library-allocated host memory released with
+ *    pms_result_free().  A hip_stream argument is borrowed (NULL = the
+ *    library's own stream).
+ *  - Thread safety: pms_solve and pms_solve_batch are reentrant; a pms_batch
+ *    is used by one thread at a time; a pms_stream accepts submissions from
+ *    any number of threads.
+ */
+#ifndef PMS_H
+#define PMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMS_OK = 0,
+    PMS_E_INVAL = -1,       /* bad n, m, l, d, count, NULL pointer or string length */
+    PMS_E_ALPHABET = -2,    /* character outside the alphabet, or repeated alphabet character */
+    PMS_E_UNSUPPORTED = -3, /* outside the GPU path's limits (|alphabet| != 4, l > 64, n > 32, ...) */
+    PMS_E_NOMEM = -4,       /* host or device allocation failed, or above the admission cap */
+    PMS_E_DEVICE = -5,      /* a HIP runtime error */
+    PMS_E_AGAIN = -6,       /* stream ticket not finished yet */
+    PMS_E_ABORTED = -7,     /* request cancelled (stream destroyed or watchdog) */
+    PMS_E_TIMEOUT = -8      /* pms_stream_wait timed out */
+} pms_status;
+
+/* One problem instance (Section 1): n strings of length m, motif length l,
+ * distance d.  seqs[i] points at S_{i+1}. */
+typedef struct {
+    const char* const* seqs;
+    int32_t n;
+    int32_t m;
+    const char* alphabet;
+    int32_t l;
+    int32_t d;
+} pms_instance;
+
+/* Sorted motif set of one instance. */
+typedef struct {
+    int64_t count;     /* number of motifs */
+    int32_t l;         /* motif length */
+    int32_t words;     /* 64-bit words per packed key (1 if l <= 32, else 2) */
+    char* motifs;      /* count*l characters, no separators, sorted, unique */
+    uint64_t* packed;  /* count*words keys: 2-bit codes, first character in the
+                          most significant bits (left-aligned), same order */
+} pms_result;
+
+/* Search parameters.  Zero / negative fields mean "choose automatically".
+ * None of them changes the result set (the method is exact for every
+ * setting); they change only speed and memory. */
+typedef struct {
+    int32_t threshold;      /* stack size t at which the search switches to
+                               neighbourhood generation (Section 2.2,
+                               Appendix D); 2..8, 0 = cost model */
+    int32_t lmer_words;     /* 1: l-mers in 2 x 32-bit planes (l <= 32);
+                               2: 2 x 64-bit planes ("128-bit"); 0 = 1 if l<=32 */
+    int32_t triple_filter;  /* >= 0: filter survivors with Theorem 1 (default),
+                               < 0: pairwise 2d filter only */
+    int32_t waves_per_cu;   /* resident search waves per CU (persistent grid); 0 = auto */
+    int32_t compat_kernel;  /* 1: VALU xor/popcount, 2: int8 one-hot MFMA; 0 = auto */
+    int32_t split;          /* work-item depth: 2 (stack prefixes of two l-mers) or
+                               3 (three); 0 = auto */
+    int64_t out_capacity;   /* initial motif slots per instance (pre-dedup); 0 = auto */
+} pms_tune;
+
+/* Solve one instance (Section 1 problem statement).  Blocks until done. */
+int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabet,
+              int32_t l, int32_t d, pms_result* out);
+
+/* Solve `count` instances of any mix of (l, d, n, m) in one device pass: one
+ * pack launch, one compat launch, one persistent search launch fed by a
+ * device work queue, one sort/unique launch.  outs[i] receives instance i's
+ * set.  tune may be NULL. */
+int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
+                    const pms_tune* tune, void* hip_stream);
+
+/* ---- device-resident batches: inputs uploaded once, solved many times ---- */
+typedef struct pms_batch pms_batch;
+
+/* Validate, encode and upload the instances; plan and allocate device memory.
+ * If workspace is non-NULL it must be device memory of at least
+ * pms_batch_workspace_size() bytes, borrowed for the batch's lifetime;
+ * otherwise the library allocates. */
+int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tune,
+                     void* workspace, size_t workspace_bytes, pms_batch** out);
+/* Device bytes a batch of these instances needs (for a caller workspace). */
+int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_tune* tune,
+                             size_t* bytes);
+/* Enqueue the whole device pipeline on hip_stream (inputs already in HBM).
+ * Asynchronous; use_graph != 0 replays a captured hipGraph of the same
+ * launches after the first call. */
+int pms_batch_run(pms_batch* b, void* hip_stream, int32_t use_graph);
+/* Wait for the last run, copy the sets back.  outs has one slot per
+ * instance.  Re-runs internally (larger output buffers) if a run overflowed. */
+int pms_batch_results(pms_batch* b, pms_result* outs);
+/* Per-phase device times of the last run in milliseconds (pack, compat,
+ * expand, search, sort), measured with HIP events on the run's stream. */
+int pms_batch_timings(pms_batch* b, float* ms5);
+int pms_batch_destroy(pms_batch* b);
+
+/* ---- serving: continuous batching with admission by device memory ---- */
+typedef struct {
+    int64_t device_mem_cap;  /* bytes the stream may hold on the device; 0 = 64 GiB */
+    int32_t max_inflight;    /* instances resident at once; 0 = 256 */
+    int32_t max_wave;        /* instances admitted per device pass; 0 = 64 */
+    pms_tune tune;
+} pms_stream_config;
+
+typedef struct pms_stream pms_stream;
+
+int pms_stream_create(const pms_stream_config* cfg, pms_stream** s);
+/* Copy the instance and queue it; returns a ticket.  PMS_E_NOMEM if the
+ * instance alone exceeds device_mem_cap. */
+int pms_stream_submit(pms_stream* s, const pms_instance* inst, uint64_t* ticket);
+/* PMS_E_AGAIN while not finished; otherwise the ticket's status and set. */
+int pms_stream_poll(pms_stream* s, uint64_t ticket, pms_result* out);
+/* Block until finished or timeout_us elapses (<0: forever). */
+int pms_stream_wait(pms_stream* s, uint64_t ticket, pms_result* out, int64_t timeout_us);
+/* Finishes in-flight work, fails queued tickets with PMS_E_ABORTED, frees. */
+int pms_stream_destroy(pms_stream* s);
+
+void pms_result_free(pms_result* r);
+const char* pms_strerror(int status);
+/* Library version string. */
+const char* pms_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMS_H */

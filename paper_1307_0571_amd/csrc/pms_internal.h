@@ -1,0 +1,97 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+namespace pms {
+
+// Limits of the device path.
+constexpr int kMaxN = 32;        // strings per instance (row bit masks are 32-bit)
+constexpr int kMaxR = 2048;      // windows per string (11-bit window index)
+constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes)
+constexpr int kMaxT = 8;         // stack size at which generation starts
+constexpr int kVCap = 512;       // survivor l-mers staged in LDS for verification
+constexpr int kCandCap = 128;    // candidate buffer in LDS
+constexpr int kNodeBatch = 16;   // generator nodes expanded per wave step (x4 children)
+constexpr int kNodeCap = 4 * kNodeBatch * kMaxL;  // node stack bound per wave (see search)
+
+// One instance as the kernels see it.
+struct InstDev {
+    int32_t n, m, l, d;
+    int32_t r;        // windows per string, m - l + 1 (0 if m < l)
+    int32_t bw;       // 64-bit words per row bitset, ceil(r / 64)
+    int32_t t;        // stack size at which neighbourhood generation starts
+    int32_t triple;   // Theorem 1 survivor filter on/off
+    int64_t chars_off;   // byte offset of the n*m characters
+    int64_t lmer_off;    // l-mer offset (units of one packed l-mer)
+    int64_t compat_off;  // u64 offset of the compat bit-matrix [N][n][bw]
+    int64_t out_off;     // key offset (units of one key)
+    int64_t out_cap;     // key slots (power of two)
+};
+
+// Per-instance device counters.
+struct InstCounters {
+    unsigned long long out_count;  // motifs emitted (with repeats)
+    unsigned long long uniq;       // distinct motifs after sort/unique
+    unsigned int flags;            // kFlag* bits
+    unsigned int pad;
+    unsigned long long items;      // level-2 work items produced
+};
+
+constexpr unsigned kFlagOutOverflow = 1u;
+constexpr unsigned kFlagItemOverflow = 2u;
+constexpr unsigned kFlagNodeOverflow = 4u;
+
+// Global queue counters.
+struct QueueCounters {
+    unsigned long long item_count;  // items appended
+    unsigned long long item_next;   // next item to take
+    unsigned long long item_cap;
+    unsigned long long pad;
+};
+
+// Generator node: prefix bit-planes, budgets (one byte per stack member), depth.
+struct Node {
+    uint64_t h, lo, bud;
+    uint32_t depth, pad;
+};
+
+struct LaunchPlan {
+    int n_inst;
+    int max_n_lmers;     // max over instances of n*r
+    int max_r;
+    int max_n;
+    int level_words;     // max over instances of n*bw (u64 words per search level)
+    int tmax;            // max threshold in the batch (template selector)
+    int words;           // l-mer width (1 or 2)
+    int search_blocks;   // persistent grid size
+    int compat_kernel;   // 1 VALU, 2 MFMA
+    int max_out_keys_lds;
+};
+
+// Device buffers of one planned batch.
+struct DevBufs {
+    InstDev* inst;
+    uint8_t* chars;
+    uint8_t* lut;
+    void* lmers;
+    uint64_t* compat;
+    uint64_t* items;
+    Node* nodes;
+    uint64_t* keys;
+    InstCounters* ctr;
+    QueueCounters* q;
+};
+
+// Kernel launchers (pms_kernels.hip).  All enqueue on `stream`.
+hipError_t launch_reset(const LaunchPlan& p, const DevBufs& b, unsigned long long item_cap,
+                        hipStream_t stream);
+hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
+hipError_t launch_compat(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
+hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
+hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
+hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
+size_t search_lds_bytes(const LaunchPlan& p);
+
+}  // namespace pms

@@ -1,0 +1,895 @@
+// gfx950 kernels for exact (l,d) planted motif search (PMS8).
+//
+// Data layout (per instance, all in HBM):
+//   chars   n*m bytes, row-major (string i at i*m)
+//   lmers   N = n*r packed l-mers, id g = row*r + window.  Planar 2-bit
+//           packing: bit p of plane h / lo is the high / low bit of the code
+//           of character p, so Hd(u,v) = popcount((u.h^v.h) | (u.lo^v.lo)).
+//           W = 1: two 32-bit planes (l <= 32); W = 2: two 64-bit planes.
+//   compat  [N][n][bw] u64 bitsets: bit x of word (u, j, x/64) is set iff
+//           Hd(u, window x of string j) <= 2d and u is not in string j
+//           (the pair condition of Section 2.4, precomputed as Section 2.1
+//           describes).
+//   keys    motif keys, 2 bits per character, first character in the most
+//           significant bits; W words per key.
+//
+// Pipeline: pack -> compat -> expand (level 1, one wave per S_1 window;
+// pushes level-2 work items to a device queue) -> search (persistent waves
+// pop items and run the rest of Algorithm 2 depth-first with per-level row
+// bitsets in LDS, the Theorem 1 survivor filter, Algorithm 1's pruned tree
+// and the candidate check) -> sort/unique.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pms_internal.h"
+
+namespace pms {
+
+template <int W> struct Lm;
+template <> struct Lm<1> { uint32_t h, lo; };
+template <> struct Lm<2> { uint64_t h, lo; };
+template <int W> struct MaskOf { typedef uint64_t type; };
+template <> struct MaskOf<1> { typedef uint32_t type; };
+
+__device__ __forceinline__ uint32_t dmask(const Lm<1>& a, const Lm<1>& b) {
+    return (a.h ^ b.h) | (a.lo ^ b.lo);
+}
+__device__ __forceinline__ uint64_t dmask(const Lm<2>& a, const Lm<2>& b) {
+    return (a.h ^ b.h) | (a.lo ^ b.lo);
+}
+__device__ __forceinline__ int pc(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ int pc(uint64_t x) { return __popcll(x); }
+// bits at positions >= s (s <= 64)
+__device__ __forceinline__ uint32_t suf(uint32_t x, int s) { return s >= 32 ? 0u : x >> s; }
+__device__ __forceinline__ uint64_t suf(uint64_t x, int s) { return s >= 64 ? 0ull : x >> s; }
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int rank_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// --------------------------------------------------------------- reset
+
+__global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigned long long item_cap) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_inst) {
+        ctr[i].out_count = 0;
+        ctr[i].uniq = 0;
+        ctr[i].flags = 0;
+        ctr[i].pad = 0;
+        ctr[i].items = 0;
+    }
+    if (i == 0) {
+        q->item_count = 0;
+        q->item_next = 0;
+        q->item_cap = item_cap;
+        q->pad = 0;
+    }
+}
+
+// ---------------------------------------------------------------- pack (a1)
+
+template <int W>
+__global__ __launch_bounds__(256) void k_pack(const InstDev* __restrict__ insts,
+                                              const uint8_t* __restrict__ chars,
+                                              const uint8_t* __restrict__ lut,
+                                              Lm<W>* __restrict__ lmers) {
+    typedef typename MaskOf<W>::type M;
+    const InstDev I = insts[blockIdx.y];
+    const int N = I.n * I.r;
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= N) return;
+    const int row = g / I.r, w = g - row * I.r;
+    const uint8_t* p = chars + I.chars_off + (int64_t)row * I.m + w;
+    const uint8_t* tab = lut + (int64_t)blockIdx.y * 256;
+    M h = 0, lo = 0;
+    for (int i = 0; i < I.l; i++) {
+        uint32_t c = tab[p[i]];
+        h |= (M)((c >> 1) & 1u) << i;
+        lo |= (M)(c & 1u) << i;
+    }
+    Lm<W> v;
+    v.h = h;
+    v.lo = lo;
+    lmers[I.lmer_off + g] = v;
+}
+
+// ------------------------------------------------- compat bit-matrix (a2)
+// One wave per (tile of 8 l-mers u, string j); lane x of word w tests window
+// 64w+x of string j against the 8 u's; each test's wave ballot is one word.
+
+constexpr int kCompatTile = 8;
+
+template <int W>
+__global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ insts,
+                                                const Lm<W>* __restrict__ lmers,
+                                                uint64_t* __restrict__ compat) {
+    const InstDev I = insts[blockIdx.y];
+    const int N = I.n * I.r;
+    if (N <= 0) return;
+    const int ntile = (N + kCompatTile - 1) / kCompatTile;
+    const int task = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (task >= ntile * I.n) return;
+    const int lane = lane_id();
+    const int tile = task / I.n, j = task - tile * I.n;
+    const int u0 = tile * kCompatTile;
+    const Lm<W>* L = lmers + I.lmer_off;
+    Lm<W> u[kCompatTile];
+    int urow[kCompatTile];
+#pragma unroll
+    for (int k = 0; k < kCompatTile; k++) {
+        int g = u0 + k;
+        if (g < N) {
+            u[k] = L[g];
+            urow[k] = g / I.r;
+        } else {
+            u[k].h = 0;
+            u[k].lo = 0;
+            urow[k] = -1;
+        }
+    }
+    const int thr = 2 * I.d;
+    uint64_t* out = compat + I.compat_off;
+    for (int w = 0; w < I.bw; w++) {
+        const int x = w * 64 + lane;
+        const bool valid = x < I.r;
+        Lm<W> v;
+        if (valid) v = L[j * I.r + x];
+        else {
+            v.h = 0;
+            v.lo = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kCompatTile; k++) {
+            if (urow[k] < 0) continue;
+            bool pred = valid && urow[k] != j && pc(dmask(u[k], v)) <= thr;
+            unsigned long long b = ballot(pred);
+            if (lane == 0) out[((int64_t)(u0 + k) * I.n + j) * I.bw + w] = b;
+        }
+    }
+}
+
+// ----------------------------------------------------- level-1 expansion
+// One wave per (instance, window u1 of S_1): the level-1 survivors of string j
+// are exactly the compat row C[u1][j] (Algorithm 2's first push and filter).
+// Picks the smallest remaining string (ties: lowest index; Section 2.1) and
+// appends one work item per survivor u2 of that string.
+// Item layout: inst << 32 | u1 << 16 | p2 << 11 | x2; p2 = 0 (string 0 is
+// never a search row) marks n == 1, where the stack {u1} is already complete.
+
+__global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ insts,
+                                                const uint64_t* __restrict__ compat,
+                                                uint64_t* __restrict__ items,
+                                                QueueCounters* __restrict__ q,
+                                                InstCounters* __restrict__ ctr) {
+    const int inst = blockIdx.y;
+    const InstDev I = insts[inst];
+    const int u1 = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (u1 >= I.r) return;
+    const int lane = lane_id();
+    const int n = I.n, bw = I.bw;
+    if (n == 1) {
+        if (lane == 0) {
+            unsigned long long at = atomicAdd(&q->item_count, 1ull);
+            if (at < q->item_cap)
+                items[at] = ((uint64_t)inst << 32) | ((uint64_t)u1 << 16);
+            else
+                atomicOr(&ctr[inst].flags, kFlagItemOverflow);
+            atomicAdd(&ctr[inst].items, 1ull);
+        }
+        return;
+    }
+    const uint64_t* C = compat + I.compat_off + (int64_t)u1 * n * bw;
+    // per-row popcounts: lanes over (row, word), rows 1..n-1
+    int best = 0x7FFFFFFF;  // (count << 5) | row
+    bool dead = false;
+    for (int j = 1; j < n; j++) {
+        int c = 0;
+        for (int w = lane; w < bw; w += 64) c += pc(C[j * bw + w]);
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        dead |= (c == 0);
+        best = min(best, (c << 5) | j);
+    }
+    if (dead) return;
+    const int p2 = best & 31;
+    // items: one per set bit of C[u1][p2], compacted with ballot + prefix sum
+    int total = best >> 5;
+    unsigned long long base = 0;
+    if (lane == 0) {
+        base = atomicAdd(&q->item_count, (unsigned long long)total);
+        atomicAdd(&ctr[inst].items, (unsigned long long)total);
+    }
+    base = __shfl(base, 0, 64);
+    if (base + (unsigned long long)total > q->item_cap) {
+        if (lane == 0) atomicOr(&ctr[inst].flags, kFlagItemOverflow);
+        return;
+    }
+    int done = 0;
+    for (int w0 = 0; w0 < bw; w0 += 64) {
+        const int w = w0 + lane;
+        uint64_t bits = (w < bw) ? C[p2 * bw + w] : 0ull;
+        const int c = pc(bits);
+        const int incl = wave_incl_scan(c);
+        int o = done + incl - c;
+        while (bits) {
+            const int b = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const uint64_t x2 = (uint64_t)(w * 64 + b);
+            items[base + o++] =
+                ((uint64_t)inst << 32) | ((uint64_t)u1 << 16) | ((uint64_t)p2 << 11) | x2;
+        }
+        done += __shfl(incl, 63, 64);
+    }
+}
+
+// --------------------------------------------------------------- search
+
+template <int W, int TMAX>
+struct SearchLds {
+    uint32_t rows[TMAX + 1];         // strings not on the stack at each level
+    int prow[TMAX + 1];              // string whose survivors are pushed next
+    int cursor[TMAX + 1];            // next window to try in that string
+    Lm<W> st[TMAX];                  // the stack
+    typename MaskOf<W>::type E[TMAX][TMAX];  // e(s_a, s_b) differing-position masks
+    int HD[TMAX][TMAX];              // Hd(s_a, s_b)
+    Lm<W> cand[kCandCap];            // complete common neighbours awaiting the check
+    Lm<W> vset[kVCap];               // staged survivors (verification)
+    uint16_t voff[kMaxN + 1];        // staged survivors of string j: [voff[j], voff[j+1])
+    int ncand;
+    int item;
+};
+
+template <int W>
+__device__ __forceinline__ uint64_t key_word(uint64_t h, uint64_t lo, int from, int to) {
+    // characters from..to-1 (to - from <= 32), first one in bits 63..62
+    uint64_t k = 0;
+    for (int p = from; p < to; p++) {
+        uint64_t c = (((h >> p) & 1ull) << 1) | ((lo >> p) & 1ull);
+        k |= c << (62 - 2 * (p - from));
+    }
+    return k;
+}
+
+template <int W, int TMAX>
+struct Searcher {
+    typedef typename MaskOf<W>::type M;
+    SearchLds<W, TMAX>& S;
+    uint64_t* lv;  // LDS level bitsets: level k at lv + (k - 2) * level_words
+    int level_words;
+    const InstDev& I;
+    int inst;
+    const Lm<W>* L;       // this instance's l-mers
+    const uint64_t* C;    // this instance's compat matrix
+    uint64_t u1g;         // global id of the level-1 l-mer (string 0)
+    Node* nodes;          // this wave's generator stack
+    uint64_t* keys;
+    InstCounters* ctr;
+    int lane;
+
+    __device__ uint64_t* level(int k) { return lv + (k - 2) * level_words; }
+
+    // Push the window px of string prow as stack member k (stack size becomes
+    // k + 1) and filter every remaining string's survivors into level k + 1:
+    // keep v iff Hd(top, v) <= 2d (compat bit) and, for every earlier member
+    // s_a, Cd(s_a, top, v) <= 3d (Theorem 1 with d1 = d2 = d3 = d; its pair
+    // conditions already hold).  Returns whether every remaining string still
+    // has a survivor (Algorithm 2's R'.size > 0).
+    __device__ bool push_filter(int k, int prow, int px) {
+        const int n = I.n, bw = I.bw, r = I.r;
+        const int ug = prow * r + px;
+        const Lm<W> top = L[ug];
+        if (lane == 0) S.st[k] = top;
+        if (lane < k) {
+            M e = dmask(S.st[lane], top);
+            S.E[lane][k] = e;
+            S.HD[lane][k] = pc(e);
+        }
+        if (lane < kMaxN) cntw[(k + 1) * kMaxN + lane] = 0u;
+        const uint32_t rows = S.rows[k] & ~(1u << prow);
+        __syncthreads();
+        const uint64_t* Cu = C + (int64_t)ug * n * bw;
+        if (k == 1)
+            filter_body(C + (int64_t)u1g * n * bw, Cu, top, k, rows);
+        else
+            filter_body(level(k), Cu, top, k, rows);
+        __syncthreads();
+        const bool bad = lane < n && ((rows >> lane) & 1u) && cnt16(k + 1, lane) == 0;
+        if (lane == 0) S.rows[k + 1] = rows;
+        __syncthreads();
+        return ballot(bad) == 0ull;
+    }
+
+    template <typename PP>
+    __device__ __forceinline__ void filter_body(PP parent, const uint64_t* Cu, const Lm<W>& top,
+                                                int k, uint32_t rows) {
+        const int bw = I.bw, r = I.r;
+        uint64_t* child = level(k + 1);
+        const int total = I.n * bw;
+        const int thr3 = 3 * I.d;
+        for (int i0 = 0; i0 < total; i0 += 64) {
+            const int i = i0 + lane;
+            const int j = i / bw;
+            if (i < total && ((rows >> j) & 1u)) {
+                const int w = i - j * bw;
+                uint64_t nb = parent[i] & Cu[i];
+                if (I.triple) {
+                    uint64_t bits = nb;
+                    while (bits) {
+                        const int b = __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        const Lm<W> v = L[j * r + w * 64 + b];
+                        const M dv = dmask(top, v);
+                        const int hv = pc(dv);
+                        bool ok = true;
+                        for (int a = 0; a < k; a++) {
+                            const M da = dmask(S.st[a], v);
+                            const int cd = S.HD[a][k] + pc(da) + hv - pc((M)(S.E[a][k] | da));
+                            ok &= cd <= thr3;
+                        }
+                        if (!ok) nb &= ~(1ull << b);
+                    }
+                }
+                child[i] = nb;
+                if (nb) atomicAdd(&cnt_word(k + 1, j), (unsigned)pc(nb));
+            }
+        }
+    }
+
+    // counts live in 32-bit LDS words for atomics; cnt16 reads them back
+    __device__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
+    __device__ unsigned cnt16(int k, int j) { return cntw[k * kMaxN + j]; }
+    unsigned* cntw;
+
+    __device__ int choose_row(int k) {
+        const uint32_t rows = S.rows[k];
+        int v = 0x7FFFFFFF;
+        if (lane < I.n && ((rows >> lane) & 1u)) v = (int)(cnt16(k, lane) << 5) | lane;
+        v = wave_min(v);
+        return v & 31;
+    }
+
+    // next survivor of string p at level k with window >= from, or -1
+    __device__ int next_bit(int k, int p, int from) {
+        const uint64_t* row = level(k) + p * I.bw;
+        int w = from >> 6;
+        if (w >= I.bw) return -1;
+        uint64_t bits = row[w] & (~0ull << (from & 63));
+        while (true) {
+            if (bits) return w * 64 + __builtin_ctzll(bits);
+            if (++w >= I.bw) return -1;
+            bits = row[w];
+        }
+    }
+
+    __device__ void emit(const Lm<W>& mv) {
+        const uint64_t h = (uint64_t)mv.h, lo = (uint64_t)mv.lo;
+        const unsigned long long at = atomicAdd(&ctr[inst].out_count, 1ull);
+        if (at < (unsigned long long)I.out_cap) {
+            uint64_t* dst = keys + (I.out_off + (int64_t)at) * W;
+            dst[0] = key_word<W>(h, lo, 0, I.l < 32 ? I.l : 32);
+            if (W == 2) dst[1] = I.l > 32 ? key_word<W>(h, lo, 32, I.l) : 0ull;
+        } else {
+            atomicOr(&ctr[inst].flags, kFlagOutOverflow);
+        }
+    }
+
+    // Check candidates cand[0..nc) against every remaining string of level k
+    // (Algorithm 2's isMotif on the filtered rows); lane c checks candidate c.
+    __device__ void verify(int k, int nc, bool staged) {
+        const Lm<W> mv = S.cand[lane < nc ? lane : 0];
+        bool ok = lane < nc;
+        const uint32_t rows = S.rows[k];
+        const int d = I.d;
+        for (int j = 0; j < I.n; j++) {
+            if (!((rows >> j) & 1u)) continue;
+            if (ballot(ok) == 0ull) break;
+            bool found = false;
+            if (staged) {
+                const int a = S.voff[j], e = S.voff[j + 1];
+                for (int q = a; q < e; q++) {
+                    found |= pc(dmask(mv, S.vset[q])) <= d;
+                    if (((q - a) & 7) == 7 && ballot(ok && !found) == 0ull) break;
+                }
+            } else {
+                const uint64_t* row = level(k) + j * I.bw;
+                for (int w = 0; w < I.bw; w++) {
+                    uint64_t bits = row[w];
+                    while (bits) {
+                        const int b = __builtin_ctzll(bits);
+                        bits &= bits - 1;
+                        found |= pc(dmask(mv, L[j * I.r + w * 64 + b])) <= d;
+                    }
+                    if (ballot(ok && !found) == 0ull) break;
+                }
+            }
+            ok &= found;
+        }
+        if (ok) emit(mv);
+    }
+
+    // Stage the survivors of level k (in string order) into LDS if they fit.
+    __device__ bool stage(int k) {
+        const uint32_t rows = S.rows[k];
+        int tot = 0;
+        for (int j = 0; j < I.n; j++) tot += ((rows >> j) & 1u) ? (int)cnt16(k, j) : 0;
+        if (tot > kVCap) return false;
+        if (lane == 0) {
+            int acc = 0;
+            for (int j = 0; j <= I.n; j++) {
+                S.voff[j] = (uint16_t)acc;
+                if (j < I.n && ((rows >> j) & 1u)) acc += (int)cnt16(k, j);
+            }
+        }
+        const uint64_t* lvk = level(k);
+        const int total = I.n * I.bw;
+        int done = 0;
+        for (int i0 = 0; i0 < total; i0 += 64) {
+            const int i = i0 + lane;
+            const int j = i / I.bw;
+            uint64_t bits = (i < total && ((rows >> j) & 1u)) ? lvk[i] : 0ull;
+            const int c = pc(bits);
+            const int incl = wave_incl_scan(c);
+            int o = done + incl - c;
+            const int w = i - j * I.bw;
+            while (bits) {
+                const int b = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                S.vset[o++] = L[j * I.r + w * 64 + b];
+            }
+            done += __shfl(incl, 63, 64);
+        }
+        __syncthreads();
+        return true;
+    }
+
+    // Algorithm 1 on the stack st[0..k) with budgets d, pruned by negative
+    // budgets, by the pair condition on suffixes (Hd > r_i + r_j) and by
+    // Theorem 1 on suffixes of every triple (Cd > r_i + r_j + r_q); a leaf is
+    // reported only with every budget >= 0.  Wave-parallel: each step pops up
+    // to 16 nodes from the top of this wave's stack and lanes evaluate their
+    // 4 children; surviving internal children are pushed (ballot + prefix
+    // sum), complete l-mers go to the candidate buffer.
+    __device__ void generate(int k) {
+        const bool staged = stage(k);
+        Lm<W> s[TMAX];
+        M e[TMAX][TMAX];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            s[a] = S.st[a < k ? a : 0];
+#pragma unroll
+            for (int b = 0; b < TMAX; b++) e[a][b] = (a < b && b < k) ? S.E[a][b] : (M)0;
+        }
+        const int l = I.l, d = I.d;
+        uint64_t bud0 = 0;
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+            if (a < k) bud0 |= (uint64_t)d << (8 * a);
+        if (lane == 0) {
+            Node rt;
+            rt.h = 0;
+            rt.lo = 0;
+            rt.bud = bud0;
+            rt.depth = 0;
+            rt.pad = 0;
+            nodes[0] = rt;
+            S.ncand = 0;
+        }
+        __syncthreads();
+        int size = 1;
+        while (size > 0) {
+            if (size > kNodeCap - 4 * kNodeBatch) {
+                // cannot happen (each depth holds at most one batch of 4*16
+                // children); kept as a guard so the stack never overruns
+                if (lane == 0) atomicOr(&ctr[inst].flags, kFlagNodeOverflow);
+                break;
+            }
+            const int B = size < kNodeBatch ? size : kNodeBatch;
+            const int base = size - B;
+            const int ni = lane >> 2;
+            const int alpha = lane & 3;
+            const bool active = ni < B;
+            Node nd;
+            if (active) nd = nodes[base + ni];
+            else {
+                nd.h = 0;
+                nd.lo = 0;
+                nd.bud = 0;
+                nd.depth = 0;
+            }
+            __syncthreads();  // every lane has read its node before pushes overwrite
+            size = base;
+            const int p = (int)nd.depth;
+            bool valid = active;
+            int rb[TMAX];
+            uint64_t nbud = 0;
+#pragma unroll
+            for (int a = 0; a < TMAX; a++) {
+                if (a < k) {
+                    const int ca = (int)((((uint64_t)s[a].h >> p) & 1ull) << 1 | (((uint64_t)s[a].lo >> p) & 1ull));
+                    int ra = (int)((nd.bud >> (8 * a)) & 0xFFull) - (ca != alpha ? 1 : 0);
+                    rb[a] = ra;
+                    valid &= ra >= 0;
+                    nbud |= (uint64_t)(ra < 0 ? 0 : ra) << (8 * a);
+                } else {
+                    rb[a] = 0;
+                }
+            }
+            const int sfx = p + 1;
+            if (valid) {
+#pragma unroll
+                for (int a = 0; a < TMAX; a++)
+#pragma unroll
+                    for (int b = a + 1; b < TMAX; b++)
+                        if (b < k) valid &= pc(suf(e[a][b], sfx)) <= rb[a] + rb[b];
+            }
+            if (valid) {
+#pragma unroll
+                for (int a = 0; a < TMAX; a++)
+#pragma unroll
+                    for (int b = a + 1; b < TMAX; b++)
+#pragma unroll
+                        for (int c = b + 1; c < TMAX; c++)
+                            if (c < k) {
+                                const M u = suf((M)(e[a][b] | e[a][c]), sfx);
+                                const M x = suf((M)(e[a][b] & e[a][c] & e[b][c]), sfx);
+                                valid &= pc(u) + pc(x) <= rb[a] + rb[b] + rb[c];
+                            }
+            }
+            const uint64_t ch = nd.h | ((uint64_t)(alpha >> 1) << p);
+            const uint64_t cl = nd.lo | ((uint64_t)(alpha & 1) << p);
+            const bool leaf = valid && sfx == l;
+            const bool push = valid && sfx < l;
+            const unsigned long long pm = ballot(push);
+            if (push) {
+                Node c;
+                c.h = ch;
+                c.lo = cl;
+                c.bud = nbud;
+                c.depth = (uint32_t)sfx;
+                c.pad = 0;
+                nodes[size + rank_below(pm)] = c;
+            }
+            size += __popcll(pm);
+            const unsigned long long lm = ballot(leaf);
+            const int nc0 = S.ncand;
+            if (leaf) {
+                Lm<W> mv;
+                mv.h = (typename MaskOf<W>::type)ch;
+                mv.lo = (typename MaskOf<W>::type)cl;
+                S.cand[nc0 + rank_below(lm)] = mv;
+            }
+            __syncthreads();
+            int nc = nc0 + __popcll(lm);
+            if (nc >= 64) {
+                verify(k, 64, staged);
+                __syncthreads();
+                const int rest = nc - 64;
+                Lm<W> mv = S.cand[64 + (lane < rest ? lane : 0)];
+                __syncthreads();
+                if (lane < rest) S.cand[lane] = mv;
+                nc = rest;
+            }
+            if (lane == 0) S.ncand = nc;
+            __syncthreads();
+        }
+        const int nc = S.ncand;
+        if (nc > 0) verify(k, nc, staged);
+        __syncthreads();
+    }
+};
+
+template <int W, int TMAX>
+__global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts,
+                                               const Lm<W>* __restrict__ lmers,
+                                               const uint64_t* __restrict__ compat,
+                                               const uint64_t* __restrict__ items,
+                                               QueueCounters* __restrict__ q,
+                                               Node* __restrict__ node_scratch,
+                                               uint64_t* __restrict__ keys,
+                                               InstCounters* __restrict__ ctr,
+                                               int level_words) {
+    extern __shared__ uint64_t dyn[];
+    __shared__ SearchLds<W, TMAX> S;
+    __shared__ unsigned cntw[(TMAX + 1) * kMaxN];
+    const int lane = lane_id();
+    Node* nodes = node_scratch + (int64_t)blockIdx.x * kNodeCap;
+    for (;;) {
+        if (lane == 0) {
+            unsigned long long it = atomicAdd(&q->item_next, 1ull);
+            S.item = it < q->item_count && it < q->item_cap ? (int)it : -1;
+        }
+        __syncthreads();
+        const int it = uni(S.item);
+        __syncthreads();
+        if (it < 0) break;
+        const uint64_t item = items[it];
+        const int inst = uni((int)(item >> 32));
+        const int u1 = uni((int)((item >> 16) & 0xFFFF));
+        const int p2 = uni((int)((item >> 11) & 31));
+        const int x2 = uni((int)(item & 0x7FF));
+        const InstDev I = insts[inst];
+        Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
+                             compat + I.compat_off, (uint64_t)u1, nodes, keys, ctr, lane};
+        sr.cntw = cntw;
+        if (lane == 0) {
+            S.st[0] = sr.L[u1];
+            S.rows[1] = (I.n >= 32 ? 0xFFFFFFFFu : ((1u << I.n) - 1u)) & ~1u;
+        }
+        __syncthreads();
+        const int t = I.t < TMAX ? I.t : TMAX;
+        if (p2 == 0) {  // n == 1: the stack {u1} is complete, nothing to check
+            if (lane == 0) S.rows[1] = 0;
+            __syncthreads();
+            sr.generate(1);
+            continue;
+        }
+        if (!sr.push_filter(1, p2, x2)) continue;
+        int k = 2;
+        bool descend = true;
+        for (;;) {
+            if (descend) {
+                if (k >= t || S.rows[k] == 0u) {
+                    sr.generate(k);
+                    k--;
+                    if (k < 2) break;
+                    descend = false;
+                    continue;
+                }
+                const int p = uni(sr.choose_row(k));
+                if (lane == 0) {
+                    S.prow[k] = p;
+                    S.cursor[k] = 0;
+                }
+                __syncthreads();
+            }
+            const int p = uni(S.prow[k]);
+            const int x = uni(sr.next_bit(k, p, S.cursor[k]));
+            __syncthreads();
+            if (x < 0) {
+                k--;
+                if (k < 2) break;
+                descend = false;
+                continue;
+            }
+            if (lane == 0) S.cursor[k] = x + 1;
+            __syncthreads();
+            if (sr.push_filter(k, p, x)) {
+                k++;
+                descend = true;
+            } else {
+                descend = false;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- sort / unique (a8)
+// One block per instance: bitonic sort of the emitted keys (LDS when they fit,
+// else in place in HBM), then drop repeats with a block prefix sum.
+
+template <int KW> struct Key { uint64_t w[KW]; };
+template <int KW>
+__device__ __forceinline__ bool key_less(const Key<KW>& a, const Key<KW>& b) {
+    if (KW == 1) return a.w[0] < b.w[0];
+    return a.w[0] < b.w[0] || (a.w[0] == b.w[0] && a.w[KW - 1] < b.w[KW - 1]);
+}
+template <int KW>
+__device__ __forceinline__ bool key_eq(const Key<KW>& a, const Key<KW>& b) {
+    bool e = true;
+#pragma unroll
+    for (int i = 0; i < KW; i++) e &= a.w[i] == b.w[i];
+    return e;
+}
+
+constexpr int kSortThreads = 1024;
+
+// One compare-exchange step of a bitonic network over P = 2^k keys; `a` is
+// either the LDS copy or the HBM array (two separate instantiations, so LDS
+// is only ever reached with ds_* instructions).
+template <int KW, typename A>
+__device__ __forceinline__ void bitonic_steps(A a, int P) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P / 2; i += kSortThreads) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = ((lo & size) == 0);
+                Key<KW> x = a.get(lo), y = a.get(hi);
+                if (key_less(y, x) == up) {
+                    a.put(lo, y);
+                    a.put(hi, x);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int KW> struct LdsKeys {
+    Key<KW>* p;
+    __device__ Key<KW> get(int i) const { return p[i]; }
+    __device__ void put(int i, const Key<KW>& v) const { p[i] = v; }
+};
+template <int KW> struct HbmKeys {
+    Key<KW>* p;
+    __device__ Key<KW> get(int i) const { return p[i]; }
+    __device__ void put(int i, const Key<KW>& v) const { p[i] = v; }
+};
+
+// Keep a[i] when i == 0 or a[i] != a[i-1]; compacted into g (block prefix sum).
+template <int KW, typename A>
+__device__ __forceinline__ int unique_into(A a, int n, Key<KW>* g, int* scan) {
+    int written = 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < n; c0 += kSortThreads) {
+        const int i = c0 + threadIdx.x;
+        Key<KW> v;
+        bool keep = false;
+        if (i < n) {
+            v = a.get(i);
+            keep = (i == 0) || !key_eq(v, a.get(i - 1));
+        }
+        const unsigned long long bm = ballot(keep);
+        __syncthreads();  // every read of this chunk precedes the writes below
+        if (lane == 0) scan[wid] = __popcll(bm);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int x = 0; x < kSortThreads / 64; x++) {
+                int tmp = scan[x];
+                scan[x] = acc;
+                acc += tmp;
+            }
+            scan[kSortThreads / 64] = acc;
+        }
+        __syncthreads();
+        if (keep) g[written + scan[wid] + rank_below(bm)] = v;
+        written += scan[kSortThreads / 64];
+        __syncthreads();
+    }
+    return written;
+}
+
+template <int KW>
+__global__ __launch_bounds__(kSortThreads) void k_sort(const InstDev* __restrict__ insts,
+                                                       uint64_t* __restrict__ keys,
+                                                       InstCounters* __restrict__ ctr) {
+    constexpr int kLdsKeys = 4096 / KW;
+    __shared__ Key<KW> sk[kLdsKeys];
+    __shared__ int scan[kSortThreads / 64 + 1];
+    const int inst = blockIdx.x;
+    const InstDev I = insts[inst];
+    const unsigned long long cnt = ctr[inst].out_count;
+    if (cnt > (unsigned long long)I.out_cap || (ctr[inst].flags & kFlagOutOverflow)) return;
+    const int n = (int)cnt;
+    if (n == 0) return;
+    int P = 1;
+    while (P < n) P <<= 1;
+    Key<KW>* g = reinterpret_cast<Key<KW>*>(keys + I.out_off * KW);
+    int written;
+    if (P <= kLdsKeys) {
+        for (int i = threadIdx.x; i < P; i += kSortThreads) {
+            if (i < n) {
+                sk[i] = g[i];
+            } else {
+#pragma unroll
+                for (int w = 0; w < KW; w++) sk[i].w[w] = ~0ull;
+            }
+        }
+        __syncthreads();
+        bitonic_steps<KW>(LdsKeys<KW>{sk}, P);
+        written = unique_into<KW>(LdsKeys<KW>{sk}, n, g, scan);
+    } else {
+        // P <= out_cap (a power of two >= n): sort in place in HBM
+        for (int i = n + threadIdx.x; i < P; i += kSortThreads) {
+#pragma unroll
+            for (int w = 0; w < KW; w++) g[i].w[w] = ~0ull;
+        }
+        __syncthreads();
+        bitonic_steps<KW>(HbmKeys<KW>{g}, P);
+        written = unique_into<KW>(HbmKeys<KW>{g}, n, g, scan);
+    }
+    if (threadIdx.x == 0) ctr[inst].uniq = (unsigned long long)written;
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_reset(const LaunchPlan& p, const DevBufs& b, unsigned long long item_cap,
+                        hipStream_t stream) {
+    int blocks = (p.n_inst + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, stream, b.ctr, p.n_inst, b.q, item_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.max_n_lmers <= 0) return hipSuccess;
+    dim3 grid((p.max_n_lmers + 255) / 256, p.n_inst);
+    if (p.words == 1)
+        hipLaunchKernelGGL(k_pack<1>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
+                           (Lm<1>*)b.lmers);
+    else
+        hipLaunchKernelGGL(k_pack<2>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
+                           (Lm<2>*)b.lmers);
+    return hipGetLastError();
+}
+
+hipError_t launch_compat(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.max_n_lmers <= 0) return hipSuccess;
+    const int ntile = (p.max_n_lmers + kCompatTile - 1) / kCompatTile;
+    const long tasks = (long)ntile * p.max_n;
+    dim3 grid((unsigned)((tasks + 3) / 4), p.n_inst);
+    if (p.words == 1)
+        hipLaunchKernelGGL(k_compat<1>, grid, dim3(256), 0, stream, b.inst, (const Lm<1>*)b.lmers,
+                           b.compat);
+    else
+        hipLaunchKernelGGL(k_compat<2>, grid, dim3(256), 0, stream, b.inst, (const Lm<2>*)b.lmers,
+                           b.compat);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.max_r <= 0) return hipSuccess;
+    dim3 grid((p.max_r + 3) / 4, p.n_inst);
+    hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, stream, b.inst, b.compat, b.items, b.q, b.ctr);
+    return hipGetLastError();
+}
+
+size_t search_lds_bytes(const LaunchPlan& p) {
+    int tm = p.tmax;
+    return (size_t)(tm > 1 ? tm - 1 : 1) * (size_t)p.level_words * 8u;
+}
+
+template <int W, int TMAX>
+static hipError_t search_t(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    const size_t lds = search_lds_bytes(p);
+    hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
+                       (const Lm<W>*)b.lmers, b.compat, b.items, b.q, b.nodes, b.keys, b.ctr,
+                       p.level_words);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t search_w(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.tmax <= 2) return search_t<W, 2>(p, b, stream);
+    if (p.tmax <= 3) return search_t<W, 3>(p, b, stream);
+    if (p.tmax <= 4) return search_t<W, 4>(p, b, stream);
+    if (p.tmax <= 5) return search_t<W, 5>(p, b, stream);
+    if (p.tmax <= 6) return search_t<W, 6>(p, b, stream);
+    return search_t<W, 8>(p, b, stream);
+}
+
+hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.max_r <= 0 || p.search_blocks <= 0) return hipSuccess;
+    return p.words == 1 ? search_w<1>(p, b, stream) : search_w<2>(p, b, stream);
+}
+
+hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    if (p.words == 1)
+        hipLaunchKernelGGL(k_sort<1>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
+                           b.ctr);
+    else
+        hipLaunchKernelGGL(k_sort<2>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
+                           b.ctr);
+    return hipGetLastError();
+}
+
+}  // namespace pms

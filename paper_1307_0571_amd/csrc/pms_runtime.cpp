@@ -1,0 +1,599 @@
+// Host runtime of libpms: validation, memory planning, launches, results.
+// The C ABI is declared in include/pms.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pms.h"
+#include "pms_internal.h"
+
+using namespace pms;
+
+namespace {
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int device_cus() {
+    static std::atomic<int> cus{0};
+    int c = cus.load();
+    if (c > 0) return c;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return 256;
+    c = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    cus.store(c);
+    return c;
+}
+
+// |N_d| for an l-mer over a 4-letter alphabet: sum_{i<=d} C(l,i) 3^i (Appendix D).
+double ball_size(int l, int d) {
+    double s = 0, c = 1;
+    for (int i = 0; i <= d && i <= l; i++) {
+        s += c * std::pow(3.0, i);
+        c = c * (l - i) / (i + 1);
+    }
+    return s;
+}
+
+}  // namespace
+
+// Stack size t at which the search switches to generation: minimise the
+// Appendix D cost model Time_s(t) + Time_p(t) over t, with p = N_2d / 4^l and
+// q = N_d / N_2d, then move one level deeper (generation and candidate checks
+// are the less regular part on a wavefront), clamped to [2, 8].
+extern "C" int pms_default_threshold(int n, int m, int l, int d) {
+    const int r = m - l + 1;
+    if (r <= 0 || n <= 1) return 2;
+    const double nd = ball_size(l, d), n2d = ball_size(l, 2 * d);
+    const double p = std::min(1.0, n2d / std::pow(4.0, l));
+    const double q = nd / n2d;
+    int best = 1;
+    double best_cost = INFINITY, ts = 0;
+    for (int t = 1; t <= n; t++) {
+        const double lt = t * std::log((double)r) + 0.5 * t * (t - 1) * std::log(p);
+        ts += (double)n * l * std::exp(std::min(lt, 700.0));
+        const double tp = std::exp(std::min(lt + std::log(nd) + (t - 1) * std::log(q), 700.0)) * l;
+        if (ts + tp < best_cost) {
+            best_cost = ts + tp;
+            best = t;
+        }
+    }
+    return std::max(2, std::min(kMaxT, best + 1));
+}
+
+namespace {
+
+struct HostInst {
+    int n, m, l, d, t, triple;
+    std::string alpha;  // sorted
+};
+
+int validate(const pms_instance& in, HostInst& h, std::vector<uint8_t>& chars,
+             std::vector<uint8_t>& lut) {
+    if (!in.seqs || !in.alphabet || in.n < 1 || in.m < 0 || in.l < 1 || in.d < 0 || in.d >= in.l)
+        return PMS_E_INVAL;
+    const size_t alen = strlen(in.alphabet);
+    std::string a(in.alphabet, alen);
+    std::sort(a.begin(), a.end());
+    for (size_t i = 1; i < a.size(); i++)
+        if (a[i] == a[i - 1]) return PMS_E_ALPHABET;
+    if (a.size() < 2) return PMS_E_ALPHABET;
+    uint8_t tab[256];
+    memset(tab, 0xFF, sizeof(tab));
+    for (size_t i = 0; i < a.size(); i++) tab[(uint8_t)a[i]] = (uint8_t)i;
+    const size_t base = chars.size();
+    chars.resize(base + (size_t)in.n * in.m);
+    for (int i = 0; i < in.n; i++) {
+        const char* s = in.seqs[i];
+        if (!s) return PMS_E_INVAL;
+        for (int j = 0; j < in.m; j++) {
+            if (s[j] == '\0') return PMS_E_INVAL;
+            if (tab[(uint8_t)s[j]] == 0xFF) return PMS_E_ALPHABET;
+        }
+        if (s[in.m] != '\0') return PMS_E_INVAL;
+        memcpy(&chars[base + (size_t)i * in.m], s, (size_t)in.m);
+    }
+    if (a.size() != 4) return PMS_E_UNSUPPORTED;
+    if (in.l > kMaxL || in.n > kMaxN || in.m - in.l + 1 > kMaxR) return PMS_E_UNSUPPORTED;
+    lut.insert(lut.end(), tab, tab + 256);
+    h.n = in.n;
+    h.m = in.m;
+    h.l = in.l;
+    h.d = in.d;
+    h.alpha = a;
+    return PMS_OK;
+}
+
+struct DevCache {
+    std::mutex mu;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    bool busy = false;
+};
+DevCache g_cache;
+
+void* cache_take(size_t bytes, bool* from_cache) {
+    std::lock_guard<std::mutex> lk(g_cache.mu);
+    *from_cache = false;
+    if (g_cache.busy) return nullptr;
+    if (g_cache.bytes < bytes) {
+        if (g_cache.ptr) (void)hipFree(g_cache.ptr);
+        g_cache.ptr = nullptr;
+        g_cache.bytes = 0;
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        g_cache.ptr = p;
+        g_cache.bytes = bytes;
+    }
+    g_cache.busy = true;
+    *from_cache = true;
+    return g_cache.ptr;
+}
+
+void cache_give(void* p) {
+    std::lock_guard<std::mutex> lk(g_cache.mu);
+    if (p == g_cache.ptr) g_cache.busy = false;
+}
+
+}  // namespace
+
+struct pms_batch {
+    std::vector<HostInst> hin;
+    std::vector<InstDev> dinst;
+    std::vector<uint8_t> chars, lut;
+    std::vector<int64_t> out_cap;
+    LaunchPlan plan{};
+    DevBufs b{};
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    bool own_arena = false;
+    bool cached_arena = false;
+    void* ext_ws = nullptr;
+    size_t ext_ws_bytes = 0;
+    unsigned long long item_cap = 0;
+    pms_tune tune{};
+    hipStream_t own_stream = nullptr;
+    hipStream_t last = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t ev[6] = {};
+    bool timed = false;
+    int words = 1;
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PMS_OK : PMS_E_DEVICE; }
+
+// Plan offsets and sizes; returns total device bytes.
+size_t plan_layout(pms_batch* bt) {
+    const int ni = (int)bt->hin.size();
+    LaunchPlan& p = bt->plan;
+    p.n_inst = ni;
+    p.words = bt->words;
+    p.max_n_lmers = 0;
+    p.max_r = 0;
+    p.max_n = 0;
+    p.level_words = 1;
+    p.tmax = 2;
+    int64_t chars_off = 0, lmer_off = 0, compat_off = 0, out_off = 0;
+    unsigned long long items = 0;
+    bt->dinst.resize(ni);
+    for (int i = 0; i < ni; i++) {
+        const HostInst& h = bt->hin[i];
+        InstDev& d = bt->dinst[i];
+        d.n = h.n;
+        d.m = h.m;
+        d.l = h.l;
+        d.d = h.d;
+        d.r = h.m >= h.l ? h.m - h.l + 1 : 0;
+        d.bw = (d.r + 63) / 64;
+        d.t = h.t;
+        d.triple = h.triple;
+        d.chars_off = chars_off;
+        d.lmer_off = lmer_off;
+        d.compat_off = compat_off;
+        d.out_off = out_off;
+        d.out_cap = bt->out_cap[i];
+        const int64_t N = (int64_t)d.n * d.r;
+        chars_off += (int64_t)h.n * h.m;
+        lmer_off += N;
+        compat_off += N * d.n * d.bw;
+        out_off += d.out_cap;
+        items += (unsigned long long)d.r * (unsigned long long)std::max(d.r, 1);
+        p.max_n_lmers = std::max<int64_t>(p.max_n_lmers, N);
+        p.max_r = std::max(p.max_r, d.r);
+        p.max_n = std::max(p.max_n, d.n);
+        p.level_words = std::max(p.level_words, d.n * d.bw);
+        p.tmax = std::max(p.tmax, d.t);
+    }
+    bt->item_cap = std::max<unsigned long long>(items, 1);
+    const int wpc = bt->tune.waves_per_cu > 0 ? bt->tune.waves_per_cu : 8;
+    p.search_blocks = device_cus() * wpc;
+    p.compat_kernel = 1;
+    const int64_t lmer_bytes = bt->words == 1 ? 8 : 16;
+    size_t off = 0;
+    auto take = [&](int64_t bytes) {
+        size_t o = off;
+        off = (size_t)align_up((int64_t)off + std::max<int64_t>(bytes, 1), 256);
+        return o;
+    };
+    size_t o_inst = take((int64_t)ni * sizeof(InstDev));
+    size_t o_chars = take(chars_off);
+    size_t o_lut = take((int64_t)ni * 256);
+    size_t o_lmers = take(lmer_off * lmer_bytes);
+    size_t o_compat = take(compat_off * 8);
+    size_t o_items = take((int64_t)bt->item_cap * 8);
+    size_t o_nodes = take((int64_t)p.search_blocks * kNodeCap * (int64_t)sizeof(Node));
+    size_t o_keys = take(out_off * 8 * bt->words);
+    size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
+    size_t o_q = take(sizeof(QueueCounters));
+    // offsets are stored relative to the arena; resolve later
+    bt->b.inst = (InstDev*)o_inst;
+    bt->b.chars = (uint8_t*)o_chars;
+    bt->b.lut = (uint8_t*)o_lut;
+    bt->b.lmers = (void*)o_lmers;
+    bt->b.compat = (uint64_t*)o_compat;
+    bt->b.items = (uint64_t*)o_items;
+    bt->b.nodes = (Node*)o_nodes;
+    bt->b.keys = (uint64_t*)o_keys;
+    bt->b.ctr = (InstCounters*)o_ctr;
+    bt->b.q = (QueueCounters*)o_q;
+    return off;
+}
+
+void resolve(pms_batch* bt) {
+    char* a = (char*)bt->arena;
+    bt->b.inst = (InstDev*)(a + (size_t)bt->b.inst);
+    bt->b.chars = (uint8_t*)(a + (size_t)bt->b.chars);
+    bt->b.lut = (uint8_t*)(a + (size_t)bt->b.lut);
+    bt->b.lmers = (void*)(a + (size_t)bt->b.lmers);
+    bt->b.compat = (uint64_t*)(a + (size_t)bt->b.compat);
+    bt->b.items = (uint64_t*)(a + (size_t)bt->b.items);
+    bt->b.nodes = (Node*)(a + (size_t)bt->b.nodes);
+    bt->b.keys = (uint64_t*)(a + (size_t)bt->b.keys);
+    bt->b.ctr = (InstCounters*)(a + (size_t)bt->b.ctr);
+    bt->b.q = (QueueCounters*)(a + (size_t)bt->b.q);
+}
+
+void release_arena(pms_batch* bt) {
+    if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->gexec = nullptr;
+    bt->graph = nullptr;
+    if (bt->arena) {
+        if (bt->cached_arena) cache_give(bt->arena);
+        else if (bt->own_arena) (void)hipFree(bt->arena);
+    }
+    bt->arena = nullptr;
+    bt->own_arena = bt->cached_arena = false;
+}
+
+// Allocate (or adopt the workspace), upload inputs.
+int materialise(pms_batch* bt, bool use_cache) {
+    const size_t need = plan_layout(bt);
+    bt->arena_bytes = need;
+    if (bt->ext_ws) {
+        if (bt->ext_ws_bytes < need) return PMS_E_NOMEM;
+        bt->arena = bt->ext_ws;
+    } else {
+        void* p = nullptr;
+        bool fc = false;
+        if (use_cache) p = cache_take(need, &fc);
+        if (!p) {
+            if (hipMalloc(&p, need) != hipSuccess) return PMS_E_NOMEM;
+            bt->own_arena = true;
+        }
+        bt->cached_arena = fc;
+        bt->arena = p;
+    }
+    resolve(bt);
+    hipError_t e;
+    e = hipMemcpy(bt->b.inst, bt->dinst.data(), bt->dinst.size() * sizeof(InstDev),
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess && !bt->chars.empty())
+        e = hipMemcpy(bt->b.chars, bt->chars.data(), bt->chars.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bt->b.lut, bt->lut.data(), bt->lut.size(), hipMemcpyHostToDevice);
+    return hip_status(e);
+}
+
+// PMS_SYNC_PHASES=1 makes every phase synchronous and names the phase that
+// reported an error (diagnostics; the default path is fully asynchronous).
+bool sync_phases() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("PMS_SYNC_PHASES");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
+    static const char* kPhase[6] = {"reset", "pack", "compat", "expand", "search", "sort"};
+    const bool sync = sync_phases() && timed;
+    hipError_t e = hipSuccess;
+    int phase = 0;
+    auto rec = [&](int i) {
+        if (timed && e == hipSuccess) e = hipEventRecord(bt->ev[i], s);
+    };
+    auto done = [&]() {
+        if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return false;
+        phase++;
+        return true;
+    };
+    rec(0);
+    bool ok = true;
+    if (ok) { e = launch_reset(bt->plan, bt->b, bt->item_cap, s); ok = done(); }
+    if (ok) { e = launch_pack(bt->plan, bt->b, s); ok = done(); }
+    rec(1);
+    if (ok) { e = launch_compat(bt->plan, bt->b, s); ok = done(); }
+    rec(2);
+    if (ok) { e = launch_expand(bt->plan, bt->b, s); ok = done(); }
+    rec(3);
+    if (ok) { e = launch_search(bt->plan, bt->b, s); ok = done(); }
+    rec(4);
+    if (ok) { e = launch_sort(bt->plan, bt->b, s); ok = done(); }
+    rec(5);
+    if (e != hipSuccess) {
+        if (sync_phases())
+            fprintf(stderr, "pms: phase %s failed: %s\n", kPhase[phase < 6 ? phase : 5],
+                    hipGetErrorString(e));
+        return PMS_E_DEVICE;
+    }
+    return PMS_OK;
+}
+
+int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pms_batch** out) {
+    if (!out || count < 0 || (count > 0 && !inst)) return PMS_E_INVAL;
+    pms_batch* bt = new (std::nothrow) pms_batch();
+    if (!bt) return PMS_E_NOMEM;
+    if (tune) bt->tune = *tune;
+    bt->hin.resize(count);
+    bool wide = bt->tune.lmer_words == 2;
+    for (int i = 0; i < count; i++) {
+        int rc = validate(inst[i], bt->hin[i], bt->chars, bt->lut);
+        if (rc) {
+            delete bt;
+            return rc;
+        }
+        HostInst& h = bt->hin[i];
+        h.t = bt->tune.threshold > 0 ? std::max(2, std::min(kMaxT, (int)bt->tune.threshold))
+                                     : pms_default_threshold(h.n, h.m, h.l, h.d);
+        h.triple = bt->tune.triple_filter < 0 ? 0 : 1;  // 0 = automatic = on
+        if (h.l > 32) wide = true;
+    }
+    if (bt->tune.lmer_words == 1 && wide) {
+        delete bt;
+        return PMS_E_UNSUPPORTED;
+    }
+    bt->words = wide ? 2 : 1;
+    const int64_t cap0 = bt->tune.out_capacity > 0 ? bt->tune.out_capacity : (1 << 14);
+    bt->out_cap.assign(count, next_pow2(cap0));
+    *out = bt;
+    return PMS_OK;
+}
+
+void fill_result(const HostInst& h, const uint64_t* keys, int64_t cnt, int kw, pms_result* r) {
+    r->count = cnt;
+    r->l = h.l;
+    r->words = h.l <= 32 ? 1 : 2;
+    r->motifs = nullptr;
+    r->packed = nullptr;
+    if (cnt == 0) return;
+    r->motifs = (char*)malloc((size_t)cnt * h.l);
+    r->packed = (uint64_t*)malloc((size_t)cnt * r->words * 8);
+    for (int64_t i = 0; i < cnt; i++) {
+        const uint64_t* k = keys + i * kw;
+        for (int p = 0; p < h.l; p++) {
+            const uint64_t w = k[p >> 5];
+            const int c = (int)((w >> (62 - 2 * (p & 31))) & 3u);
+            r->motifs[i * h.l + p] = h.alpha[c];
+        }
+        for (int q = 0; q < r->words; q++) r->packed[i * r->words + q] = k[q];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pms_version(void) { return "pms-mi355x 0.1 (gfx950)"; }
+
+const char* pms_strerror(int s) {
+    switch (s) {
+        case PMS_OK: return "ok";
+        case PMS_E_INVAL: return "invalid argument";
+        case PMS_E_ALPHABET: return "character outside the alphabet or repeated alphabet character";
+        case PMS_E_UNSUPPORTED: return "outside the GPU path's limits";
+        case PMS_E_NOMEM: return "out of memory or above the admission cap";
+        case PMS_E_DEVICE: return "HIP runtime error";
+        case PMS_E_AGAIN: return "not finished yet";
+        case PMS_E_ABORTED: return "aborted";
+        case PMS_E_TIMEOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+void pms_result_free(pms_result* r) {
+    if (!r) return;
+    free(r->motifs);
+    free(r->packed);
+    r->motifs = nullptr;
+    r->packed = nullptr;
+    r->count = 0;
+}
+
+int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_tune* tune,
+                             size_t* bytes) {
+    if (!bytes) return PMS_E_INVAL;
+    pms_batch* bt = nullptr;
+    int rc = make_batch(inst, count, tune, &bt);
+    if (rc) return rc;
+    *bytes = plan_layout(bt);
+    delete bt;
+    return PMS_OK;
+}
+
+static int batch_create_impl(const pms_instance* inst, int32_t count, const pms_tune* tune,
+                             void* ws, size_t ws_bytes, bool use_cache, pms_batch** out) {
+    pms_batch* bt = nullptr;
+    int rc = make_batch(inst, count, tune, &bt);
+    if (rc) return rc;
+    bt->ext_ws = ws;
+    bt->ext_ws_bytes = ws_bytes;
+    rc = materialise(bt, use_cache);
+    if (rc == PMS_OK) {
+        for (int i = 0; i < 6 && rc == PMS_OK; i++) rc = hip_status(hipEventCreate(&bt->ev[i]));
+    }
+    if (rc) {
+        pms_batch_destroy(bt);
+        return rc;
+    }
+    *out = bt;
+    return PMS_OK;
+}
+
+int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tune,
+                     void* workspace, size_t workspace_bytes, pms_batch** out) {
+    return batch_create_impl(inst, count, tune, workspace, workspace_bytes, false, out);
+}
+
+int pms_batch_run(pms_batch* bt, void* hip_stream, int32_t use_graph) {
+    if (!bt) return PMS_E_INVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (!s) {
+        if (!bt->own_stream && hipStreamCreate(&bt->own_stream) != hipSuccess) return PMS_E_DEVICE;
+        s = bt->own_stream;
+    }
+    bt->last = s;
+    if (!use_graph) {
+        bt->timed = true;
+        return enqueue(bt, s, true);
+    }
+    bt->timed = false;
+    if (!bt->gexec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return PMS_E_DEVICE;
+        int rc = enqueue(bt, s, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : PMS_E_DEVICE;
+        }
+        bt->graph = g;
+        if (hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            bt->gexec = nullptr;
+            return PMS_E_DEVICE;
+        }
+    }
+    return hip_status(hipGraphLaunch(bt->gexec, s));
+}
+
+int pms_batch_timings(pms_batch* bt, float* ms5) {
+    if (!bt || !ms5) return PMS_E_INVAL;
+    if (!bt->timed) return PMS_E_AGAIN;
+    if (hipEventSynchronize(bt->ev[5]) != hipSuccess) return PMS_E_DEVICE;
+    for (int i = 0; i < 5; i++)
+        if (hipEventElapsedTime(&ms5[i], bt->ev[i], bt->ev[i + 1]) != hipSuccess) return PMS_E_DEVICE;
+    return PMS_OK;
+}
+
+int pms_batch_results(pms_batch* bt, pms_result* outs) {
+    if (!bt || (!outs && !bt->hin.empty())) return PMS_E_INVAL;
+    hipStream_t s = bt->last;
+    if (!s) return PMS_E_INVAL;
+    const int ni = (int)bt->hin.size();
+    for (int attempt = 0; attempt < 8; attempt++) {
+        if (hipStreamSynchronize(s) != hipSuccess) return PMS_E_DEVICE;
+        std::vector<InstCounters> ctr(ni);
+        if (ni && hipMemcpy(ctr.data(), bt->b.ctr, ni * sizeof(InstCounters),
+                            hipMemcpyDeviceToHost) != hipSuccess)
+            return PMS_E_DEVICE;
+        bool regrow = false;
+        for (int i = 0; i < ni; i++) {
+            if (ctr[i].flags & (kFlagItemOverflow | kFlagNodeOverflow)) return PMS_E_NOMEM;
+            if ((ctr[i].flags & kFlagOutOverflow) || ctr[i].out_count > (unsigned long long)bt->out_cap[i]) {
+                bt->out_cap[i] = next_pow2((int64_t)ctr[i].out_count);
+                regrow = true;
+            }
+        }
+        if (regrow) {
+            // larger output slots: re-plan, re-upload, run again (same result set)
+            void* ws = bt->ext_ws;
+            release_arena(bt);
+            bt->ext_ws = ws;
+            int rc = materialise(bt, false);
+            if (rc) return rc;
+            rc = enqueue(bt, s, true);
+            if (rc) return rc;
+            bt->timed = true;
+            continue;
+        }
+        const int kw = bt->words;
+        for (int i = 0; i < ni; i++) {
+            const int64_t u = (int64_t)ctr[i].uniq;
+            std::vector<uint64_t> keys((size_t)u * kw);
+            if (u > 0 && hipMemcpy(keys.data(), bt->b.keys + bt->dinst[i].out_off * kw,
+                                   (size_t)u * kw * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                return PMS_E_DEVICE;
+            fill_result(bt->hin[i], keys.data(), u, kw, &outs[i]);
+        }
+        return PMS_OK;
+    }
+    return PMS_E_NOMEM;
+}
+
+int pms_batch_destroy(pms_batch* bt) {
+    if (!bt) return PMS_OK;
+    if (bt->last) (void)hipStreamSynchronize(bt->last);
+    release_arena(bt);
+    for (int i = 0; i < 6; i++)
+        if (bt->ev[i]) (void)hipEventDestroy(bt->ev[i]);
+    if (bt->own_stream) (void)hipStreamDestroy(bt->own_stream);
+    delete bt;
+    return PMS_OK;
+}
+
+int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
+                    const pms_tune* tune, void* hip_stream) {
+    if (count < 0 || (count > 0 && (!inst || !outs))) return PMS_E_INVAL;
+    for (int i = 0; i < count; i++) outs[i] = pms_result{};
+    if (count == 0) return PMS_OK;
+    pms_batch* bt = nullptr;
+    int rc = batch_create_impl(inst, count, tune, nullptr, 0, true, &bt);
+    if (rc) return rc;
+    rc = pms_batch_run(bt, hip_stream, 0);
+    if (!rc) rc = pms_batch_results(bt, outs);
+    pms_batch_destroy(bt);
+    if (rc)
+        for (int i = 0; i < count; i++) pms_result_free(&outs[i]);
+    return rc;
+}
+
+int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabet, int32_t l,
+              int32_t d, pms_result* out) {
+    if (!out) return PMS_E_INVAL;
+    pms_instance in{seqs, n, m, alphabet, l, d};
+    return pms_solve_batch(&in, 1, out, nullptr, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+"""Python binding of libpms (ctypes).  Argument marshalling only: every step
+of the search runs in the library's HIP kernels.  torch, when used, only
+provides device memory (a batch workspace) and the HIP stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpms.so")
+
+PMS_OK = 0
+PMS_E_INVAL = -1
+PMS_E_ALPHABET = -2
+PMS_E_UNSUPPORTED = -3
+PMS_E_NOMEM = -4
+PMS_E_DEVICE = -5
+PMS_E_AGAIN = -6
+PMS_E_ABORTED = -7
+PMS_E_TIMEOUT = -8
+
+
+class PmsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})" if what else strerror(status))
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("seqs", ctypes.POINTER(ctypes.c_char_p)), ("n", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("alphabet", ctypes.c_char_p),
+                ("l", ctypes.c_int32), ("d", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("l", ctypes.c_int32), ("words", ctypes.c_int32),
+                ("motifs", ctypes.POINTER(ctypes.c_char)),
+                ("packed", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class Tune(ctypes.Structure):
+    """Search parameters (0 = automatic); none of them changes the result."""
+    _fields_ = [("threshold", ctypes.c_int32), ("lmer_words", ctypes.c_int32),
+                ("triple_filter", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("compat_kernel", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("out_capacity", ctypes.c_int64)]
+
+    def __init__(self, threshold=0, lmer_words=0, triple_filter=0, waves_per_cu=0,
+                 compat_kernel=0, split=0, out_capacity=0):
+        super().__init__(threshold, lmer_words, triple_filter, waves_per_cu, compat_kernel,
+                         split, out_capacity)
+
+
+class _StreamConfig(ctypes.Structure):
+    _fields_ = [("device_mem_cap", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_wave", ctypes.c_int32), ("tune", Tune)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpms.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1307_0571_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.pms_solve.argtypes = [P(ctypes.c_char_p), ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                              ctypes.c_int32, ctypes.c_int32, P(_Result)]
+    lib.pms_solve_batch.argtypes = [P(_Instance), ctypes.c_int32, P(_Result), P(Tune), vp]
+    lib.pms_batch_create.argtypes = [P(_Instance), ctypes.c_int32, P(Tune), vp, ctypes.c_size_t,
+                                     P(vp)]
+    lib.pms_batch_workspace_size.argtypes = [P(_Instance), ctypes.c_int32, P(Tune),
+                                             P(ctypes.c_size_t)]
+    lib.pms_batch_run.argtypes = [vp, vp, ctypes.c_int32]
+    lib.pms_batch_results.argtypes = [vp, P(_Result)]
+    lib.pms_batch_timings.argtypes = [vp, P(ctypes.c_float)]
+    lib.pms_batch_destroy.argtypes = [vp]
+    lib.pms_stream_create.argtypes = [P(_StreamConfig), P(vp)]
+    lib.pms_stream_submit.argtypes = [vp, P(_Instance), P(ctypes.c_uint64)]
+    lib.pms_stream_poll.argtypes = [vp, ctypes.c_uint64, P(_Result)]
+    lib.pms_stream_wait.argtypes = [vp, ctypes.c_uint64, P(_Result), ctypes.c_int64]
+    lib.pms_stream_destroy.argtypes = [vp]
+    lib.pms_result_free.argtypes = [P(_Result)]
+    lib.pms_result_free.restype = None
+    lib.pms_strerror.argtypes = [ctypes.c_int]
+    lib.pms_strerror.restype = ctypes.c_char_p
+    lib.pms_version.restype = ctypes.c_char_p
+    lib.pms_default_threshold.argtypes = [ctypes.c_int] * 4
+    for f in ("pms_solve", "pms_solve_batch", "pms_batch_create", "pms_batch_workspace_size",
+              "pms_batch_run", "pms_batch_results", "pms_batch_timings", "pms_batch_destroy",
+              "pms_stream_create", "pms_stream_submit", "pms_stream_poll", "pms_stream_wait",
+              "pms_stream_destroy", "pms_default_threshold"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().pms_strerror(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def default_threshold(n: int, m: int, l: int, d: int) -> int:
+    return int(load().pms_default_threshold(n, m, l, d))
+
+
+@dataclass
+class Problem:
+    """One instance: strings, motif length l, distance d, alphabet."""
+    seqs: Sequence[str]
+    l: int
+    d: int
+    alphabet: str = "ACGT"
+
+
+class _Marshal:
+    """Keeps the C views of a list of problems alive."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        self.keep = []
+        self.arr = (_Instance * max(1, len(problems)))()
+        for i, p in enumerate(problems):
+            enc = [s.encode("latin-1") for s in p.seqs]
+            seqs = (ctypes.c_char_p * max(1, len(enc)))(*enc)
+            alpha = p.alphabet.encode("latin-1")
+            self.keep.append((enc, seqs, alpha))
+            m = len(p.seqs[0]) if len(p.seqs) else 0
+            self.arr[i] = _Instance(seqs, len(p.seqs), m, alpha, p.l, p.d)
+        self.count = len(problems)
+
+
+def _take(res: _Result) -> List[str]:
+    lib = load()
+    try:
+        if res.count == 0:
+            return []
+        raw = ctypes.string_at(res.motifs, res.count * res.l).decode("latin-1")
+        return [raw[i * res.l:(i + 1) * res.l] for i in range(res.count)]
+    finally:
+        lib.pms_result_free(ctypes.byref(res))
+
+
+def _check(rc: int, what: str):
+    if rc != PMS_OK:
+        raise PmsError(rc, what)
+
+
+def solve(seqs: Sequence[str], l: int, d: int, alphabet: str = "ACGT") -> List[str]:
+    """pms_solve: the sorted motif set of one instance."""
+    return solve_batch([Problem(seqs, l, d, alphabet)])[0]
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # a torch.cuda.Stream
+
+
+def solve_batch(problems: Sequence[Problem], tune: Optional[Tune] = None,
+                stream=None) -> List[List[str]]:
+    """pms_solve_batch: every instance in one device pass."""
+    lib = load()
+    mar = _Marshal(problems)
+    res = (_Result * max(1, mar.count))()
+    rc = lib.pms_solve_batch(mar.arr, mar.count, res, ctypes.byref(tune) if tune else None,
+                             _stream_ptr(stream))
+    _check(rc, "pms_solve_batch")
+    return [_take(res[i]) for i in range(mar.count)]
+
+
+class Batch:
+    """Device-resident batch: inputs uploaded once, then run many times.
+
+    With ``torch_workspace=True`` the device memory is a torch uint8 tensor
+    (the library borrows it); otherwise the library allocates its own."""
+
+    def __init__(self, problems: Sequence[Problem], tune: Optional[Tune] = None,
+                 torch_workspace: bool = False):
+        lib = load()
+        self.mar = _Marshal(problems)
+        self.tune = tune
+        self.ws = None
+        ptr, size = None, 0
+        tp = ctypes.byref(tune) if tune else None
+        if torch_workspace:
+            import torch
+            sz = ctypes.c_size_t(0)
+            _check(lib.pms_batch_workspace_size(self.mar.arr, self.mar.count, tp,
+                                                ctypes.byref(sz)), "pms_batch_workspace_size")
+            self.ws = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
+            ptr, size = self.ws.data_ptr(), int(sz.value)
+        h = ctypes.c_void_p()
+        _check(lib.pms_batch_create(self.mar.arr, self.mar.count, tp, ptr, size, ctypes.byref(h)),
+               "pms_batch_create")
+        self.h = h
+
+    def run(self, stream=None, graph: bool = False):
+        _check(load().pms_batch_run(self.h, _stream_ptr(stream), int(graph)), "pms_batch_run")
+
+    def results(self) -> List[List[str]]:
+        res = (_Result * max(1, self.mar.count))()
+        _check(load().pms_batch_results(self.h, res), "pms_batch_results")
+        return [_take(res[i]) for i in range(self.mar.count)]
+
+    def timings(self) -> List[float]:
+        arr = (ctypes.c_float * 5)()
+        _check(load().pms_batch_timings(self.h, arr), "pms_batch_timings")
+        return list(arr)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pms_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """pms_stream_*: continuous batching of submitted instances."""
+
+    def __init__(self, device_mem_cap: int = 0, max_inflight: int = 0, max_wave: int = 0,
+                 tune: Optional[Tune] = None):
+        lib = load()
+        cfg = _StreamConfig(device_mem_cap, max_inflight, max_wave, tune or Tune())
+        h = ctypes.c_void_p()
+        _check(lib.pms_stream_create(ctypes.byref(cfg), ctypes.byref(h)), "pms_stream_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, p: Problem) -> int:
+        mar = _Marshal([p])
+        t = ctypes.c_uint64(0)
+        _check(load().pms_stream_submit(self.h, mar.arr, ctypes.byref(t)), "pms_stream_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        res = _Result()
+        rc = load().pms_stream_poll(self.h, ticket, ctypes.byref(res))
+        if rc == PMS_E_AGAIN:
+            return None
+        _check(rc, "pms_stream_poll")
+        return _take(res)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> List[str]:
+        res = _Result()
+        _check(load().pms_stream_wait(self.h, ticket, ctypes.byref(res), timeout_us),
+               "pms_stream_wait")
+        return _take(res)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pms_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,116 @@
+"""GPU path (through the C ABI) against the CPU oracle: identical sorted sets."""
+import sys
+
+import pytest
+
+import oracle
+from paper_1307_0571_amd import instances as I
+from paper_1307_0571_amd import pms
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(inst, tune=None):
+    return pms.solve_batch([pms.Problem(inst.seqs, inst.l, inst.d, inst.alphabet)], tune=tune)[0]
+
+
+SMALL = [
+    # (seed, l, d, n, m): several tiles, ragged tails (r not a multiple of 64)
+    (1, 6, 1, 5, 70), (2, 7, 2, 6, 130), (3, 8, 2, 8, 200), (4, 9, 2, 10, 257),
+    (5, 10, 3, 6, 150), (6, 5, 1, 3, 64), (7, 8, 1, 2, 100), (8, 9, 3, 4, 90),
+    (9, 12, 3, 7, 129), (10, 6, 2, 1, 40), (11, 33, 8, 5, 120), (12, 40, 12, 4, 100),
+]
+
+
+@pytest.mark.parametrize("seed,l,d,n,m", SMALL)
+def test_small_vs_oracle(seed, l, d, n, m):
+    _say(f"case seed={seed} l={l} d={d} n={n} m={m}")
+    inst = I.planted(seed, l, d, n, m)
+    want = oracle.solve_a(inst.seqs, l, d) if l <= 12 else oracle.solve_b(inst.seqs, l, d)
+    got = _gpu(inst)
+    assert got == want
+    assert inst.motif in got
+
+
+def test_edge_cases():
+    _say("edge cases")
+    # m < l: no window, empty set
+    assert pms.solve(["ACG", "TTA"], 4, 1) == []
+    # one window per string
+    assert pms.solve(["ACGT", "ACGT"], 4, 0) == ["ACGT"]
+    # d = 0: exact common l-mers
+    assert pms.solve(["AACCGT", "CCAATT"], 2, 0) == ["AA", "CC"]
+    # a single string: every l-mer within d of one of its windows
+    got = pms.solve(["ACGTA"], 3, 1)
+    assert got == oracle.solve_a(["ACGTA"], 3, 1)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_92_full_size(seed):
+    _say(f"(9,2) n=20 m=600 seed={seed}")
+    inst = I.planted(seed, 9, 2)
+    assert _gpu(inst) == oracle.solve_a(inst.seqs, 9, 2)
+
+
+@pytest.mark.parametrize("l,d", [(13, 4), (15, 5)])
+def test_plain_gpu_config_seed0(l, d):
+    _say(f"({l},{d}) n=20 m=600 seed=0")
+    inst = I.planted(0, l, d)
+    want = oracle.solve_b(inst.seqs, l, d, t=3)
+    got = _gpu(inst)
+    assert got == want
+    assert inst.motif in got
+
+
+@pytest.mark.parametrize("tune", [
+    dict(threshold=2), dict(threshold=3), dict(threshold=4), dict(threshold=6),
+    dict(triple_filter=-1), dict(lmer_words=2), dict(waves_per_cu=1), dict(out_capacity=1),
+])
+def test_output_invariant_under_tuning(tune):
+    _say(f"tune {tune}")
+    inst = I.planted(21, 11, 3, 12, 300)
+    want = oracle.solve_b(inst.seqs, 11, 3)
+    assert _gpu(inst, pms.Tune(**tune)) == want
+
+
+def test_batch_equals_alone():
+    _say("batch of mixed instances")
+    insts = I.batch_mix(1000, 6, ld=((9, 2), (10, 3), (11, 3)), n_range=(5, 12),
+                        m_range=(100, 300))
+    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+    batch = pms.solve_batch(probs)
+    for x, got in zip(insts, batch):
+        assert got == oracle.solve_b(x.seqs, x.l, x.d)
+        assert got == _gpu(x)
+
+
+def test_device_batch_rerun_and_graph():
+    _say("device-resident batch, eager and graph replays")
+    insts = [I.planted(s, 10, 2, 10, 200) for s in range(3)]
+    want = [oracle.solve_b(x.seqs, 10, 2) for x in insts]
+    b = pms.Batch([pms.Problem(x.seqs, x.l, x.d) for x in insts])
+    try:
+        for graph in (False, True, True, False, True):
+            b.run(graph=graph)
+            assert b.results() == want
+    finally:
+        b.close()
+
+
+def test_torch_workspace_and_stream():
+    import torch
+    _say("torch workspace + torch stream")
+    inst = I.planted(5, 9, 2, 12, 250)
+    want = oracle.solve_a(inst.seqs, 9, 2)
+    s = torch.cuda.Stream()
+    b = pms.Batch([pms.Problem(inst.seqs, 9, 2)], torch_workspace=True)
+    try:
+        b.run(stream=s)
+        assert b.results() == [want]
+    finally:
+        b.close()
