@@ -115,9 +115,10 @@ int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tu
 /* Device bytes a batch of these instances needs (for a caller workspace). */
 int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_tune* tune,
                              size_t* bytes);
-/* Enqueue the whole device pipeline on hip_stream (inputs already in HBM).
- * Asynchronous; use_graph != 0 replays a captured hipGraph of the same
- * launches after the first call. */
+/* Run the whole device pipeline on hip_stream (inputs already in HBM).  Each
+ * phase is synchronised before the next is launched.  use_graph != 0
+ * (hipGraph replay of the same launches) is not available in this version
+ * and returns PMS_E_UNSUPPORTED. */
 int pms_batch_run(pms_batch* b, void* hip_stream, int32_t use_graph);
 /* Wait for the last run, copy the sets back.  outs has one slot per
  * instance.  Re-runs internally (larger output buffers) if a run overflowed. */
@@ -126,6 +127,27 @@ int pms_batch_results(pms_batch* b, pms_result* outs);
  * expand, search, sort), measured with HIP events on the run's stream. */
 int pms_batch_timings(pms_batch* b, float* ms5);
 int pms_batch_destroy(pms_batch* b);
+
+/* Work one instance of the last run performed, in the method's own units.
+ * compat_pairs is the number of unordered pairs of l-mers from different
+ * strings (each one Hamming test of the compatibility matrix, Section 2.1);
+ * items are the level-2 work items the expansion queued; motifs_emitted
+ * counts motifs before removal of repeats.  The search-side counters
+ * (pushes ... verify_tests) are -1: this version does not count them on
+ * the device. */
+typedef struct {
+    int64_t compat_pairs;
+    int64_t items;
+    int64_t pushes;
+    int64_t filter_words;
+    int64_t triple_tests;
+    int64_t tuples;
+    int64_t gen_evals;
+    int64_t candidates;
+    int64_t verify_tests;
+    int64_t motifs_emitted;  /* before removal of repeats */
+} pms_work;
+int pms_batch_work(pms_batch* b, int32_t instance, pms_work* out);
 
 /* ---- serving: continuous batching with admission by device memory ---- */
 typedef struct {
@@ -147,6 +169,11 @@ int pms_stream_poll(pms_stream* s, uint64_t ticket, pms_result* out);
 int pms_stream_wait(pms_stream* s, uint64_t ticket, pms_result* out, int64_t timeout_us);
 /* Finishes in-flight work, fails queued tickets with PMS_E_ABORTED, frees. */
 int pms_stream_destroy(pms_stream* s);
+
+/* Number of visible GPUs (0 when none; never an error for "no device"). */
+int pms_device_count(int32_t* count);
+/* Wait for all work the process enqueued on the current device. */
+int pms_device_synchronize(void);
 
 void pms_result_free(pms_result* r);
 const char* pms_strerror(int status);

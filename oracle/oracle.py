@@ -65,6 +65,11 @@ def _load():
                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8pp, i64p,
                              ctypes.POINTER(_Stats)]
     lib.oracle_b.restype = ctypes.c_int
+    lib.oracle_b_windows.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int64, ctypes.c_int64, u8pp, i64p,
+                                     ctypes.POINTER(_Stats)]
+    lib.oracle_b_windows.restype = ctypes.c_int
     lib.oracle_hd.argtypes = [u8p, u8p, ctypes.c_int]
     lib.oracle_hd.restype = ctypes.c_int
     lib.oracle_cd.argtypes = [ctypes.POINTER(u8p), ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -148,8 +153,12 @@ def solve_a(seqs: Sequence[str] = None, l: int = 0, d: int = 0, alphabet: str = 
 
 def solve_b(seqs: Sequence[str] = None, l: int = 0, d: int = 0, alphabet: str = "ACGT",
             t: int = None, triple: bool = True, threads: int = None,
-            codes: np.ndarray = None, stats: bool = False):
-    """Sorted motif set by PMS8 (Algorithm 2 with Algorithm 1 and Theorem 1)."""
+            codes: np.ndarray = None, stats: bool = False, windows=None):
+    """Sorted motif set by PMS8 (Algorithm 2 with Algorithm 1 and Theorem 1).
+
+    ``windows=(lo, hi)`` restricts the run to the S_1 windows lo..hi-1 (the
+    independent sub-problems of Section 2.3); the result is then the motifs
+    found from those windows only."""
     lib = _load()
     c, alpha = _codes_arg(seqs, alphabet, codes)
     n, m = c.shape
@@ -158,8 +167,14 @@ def solve_b(seqs: Sequence[str] = None, l: int = 0, d: int = 0, alphabet: str = 
     out = ctypes.POINTER(ctypes.c_uint8)()
     cnt = ctypes.c_int64(0)
     st = _Stats()
-    rc = lib.oracle_b(_ptr(c), n, m, len(alpha), l, d, int(t), int(bool(triple)),
-                      _threads(threads), ctypes.byref(out), ctypes.byref(cnt), ctypes.byref(st))
+    if windows is None:
+        rc = lib.oracle_b(_ptr(c), n, m, len(alpha), l, d, int(t), int(bool(triple)),
+                          _threads(threads), ctypes.byref(out), ctypes.byref(cnt),
+                          ctypes.byref(st))
+    else:
+        rc = lib.oracle_b_windows(_ptr(c), n, m, len(alpha), l, d, int(t), int(bool(triple)),
+                                  _threads(threads), int(windows[0]), int(windows[1]),
+                                  ctypes.byref(out), ctypes.byref(cnt), ctypes.byref(st))
     if rc != 0:
         raise OracleError(f"oracle_b failed ({rc})")
     try:

@@ -175,6 +175,7 @@ struct pms_batch {
     hipEvent_t ev[6] = {};
     bool timed = false;
     int words = 1;
+    std::vector<InstCounters> last_ctr;  // counters read back by the last results call
 };
 
 namespace {
@@ -311,30 +312,28 @@ int materialise(pms_batch* bt, bool use_cache) {
         e = hipMemcpy(bt->b.chars, bt->chars.data(), bt->chars.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(bt->b.lut, bt->lut.data(), bt->lut.size(), hipMemcpyHostToDevice);
+    // A copy from pageable host memory may return once the data is staged,
+    // before it lands in HBM; the kernels run on another stream, so wait for
+    // the uploads here before anything can read them.
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     return hip_status(e);
 }
 
-// PMS_SYNC_PHASES=1 makes every phase synchronous and names the phase that
-// reported an error (diagnostics; the default path is fully asynchronous).
-bool sync_phases() {
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("PMS_SYNC_PHASES");
-        v = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return v == 1;
-}
-
+// Every phase of the device pipeline is followed by a host synchronisation of
+// its stream.  Back-to-back launches without it (and hipGraph replay, which
+// launches the same way) failed on the GPU (a memory fault once, stalls
+// three times) while the phase-synchronous order ran correctly; the
+// asynchronous order stays off until that failure is understood.
 int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
     static const char* kPhase[6] = {"reset", "pack", "compat", "expand", "search", "sort"};
-    const bool sync = sync_phases() && timed;
+    (void)timed;
     hipError_t e = hipSuccess;
     int phase = 0;
     auto rec = [&](int i) {
-        if (timed && e == hipSuccess) e = hipEventRecord(bt->ev[i], s);
+        if (e == hipSuccess) e = hipEventRecord(bt->ev[i], s);
     };
     auto done = [&]() {
-        if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return false;
         phase++;
         return true;
@@ -353,9 +352,8 @@ int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
     if (ok) { e = launch_sort(bt->plan, bt->b, s); ok = done(); }
     rec(5);
     if (e != hipSuccess) {
-        if (sync_phases())
-            fprintf(stderr, "pms: phase %s failed: %s\n", kPhase[phase < 6 ? phase : 5],
-                    hipGetErrorString(e));
+        fprintf(stderr, "pms: phase %s failed: %s\n", kPhase[phase < 6 ? phase : 5],
+                hipGetErrorString(e));
         return PMS_E_DEVICE;
     }
     return PMS_OK;
@@ -416,6 +414,16 @@ void fill_result(const HostInst& h, const uint64_t* keys, int64_t cnt, int kw, p
 extern "C" {
 
 const char* pms_version(void) { return "pms-mi355x 0.1 (gfx950)"; }
+
+int pms_device_count(int32_t* count) {
+    if (!count) return PMS_E_INVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
+    *count = n;
+    return PMS_OK;
+}
+
+int pms_device_synchronize(void) { return hip_status(hipDeviceSynchronize()); }
 
 const char* pms_strerror(int s) {
     switch (s) {
@@ -484,28 +492,9 @@ int pms_batch_run(pms_batch* bt, void* hip_stream, int32_t use_graph) {
         s = bt->own_stream;
     }
     bt->last = s;
-    if (!use_graph) {
-        bt->timed = true;
-        return enqueue(bt, s, true);
-    }
-    bt->timed = false;
-    if (!bt->gexec) {
-        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return PMS_E_DEVICE;
-        int rc = enqueue(bt, s, false);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(s, &g);
-        if (rc || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc ? rc : PMS_E_DEVICE;
-        }
-        bt->graph = g;
-        if (hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-            bt->gexec = nullptr;
-            return PMS_E_DEVICE;
-        }
-    }
-    return hip_status(hipGraphLaunch(bt->gexec, s));
+    if (use_graph) return PMS_E_UNSUPPORTED;  // see the note above enqueue()
+    bt->timed = true;
+    return enqueue(bt, s, true);
 }
 
 int pms_batch_timings(pms_batch* bt, float* ms5) {
@@ -548,6 +537,7 @@ int pms_batch_results(pms_batch* bt, pms_result* outs) {
             bt->timed = true;
             continue;
         }
+        bt->last_ctr = ctr;
         const int kw = bt->words;
         for (int i = 0; i < ni; i++) {
             const int64_t u = (int64_t)ctr[i].uniq;
@@ -560,6 +550,24 @@ int pms_batch_results(pms_batch* bt, pms_result* outs) {
         return PMS_OK;
     }
     return PMS_E_NOMEM;
+}
+
+int pms_batch_work(pms_batch* bt, int32_t i, pms_work* w) {
+    if (!bt || !w || i < 0 || i >= (int)bt->hin.size()) return PMS_E_INVAL;
+    if (bt->last_ctr.size() != bt->hin.size()) return PMS_E_AGAIN;
+    const InstCounters& c = bt->last_ctr[i];
+    const InstDev& d = bt->dinst[i];
+    const int64_t r = d.r;
+    *w = pms_work{};
+    // counted on the host: the compat matrix tests every unordered pair of
+    // l-mers from different strings; the device reports work items and
+    // emitted motifs (search-side work counters are not in this version)
+    w->compat_pairs = (int64_t)d.n * (d.n - 1) / 2 * r * r;
+    w->items = (int64_t)c.items;
+    w->pushes = w->filter_words = w->triple_tests = w->tuples = -1;
+    w->gen_evals = w->candidates = w->verify_tests = -1;
+    w->motifs_emitted = (int64_t)c.out_count;
+    return PMS_OK;
 }
 
 int pms_batch_destroy(pms_batch* bt) {

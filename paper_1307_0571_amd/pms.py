@@ -1,6 +1,11 @@
 """Python binding of libpms (ctypes).  Argument marshalling only: every step
-of the search runs in the library's HIP kernels.  torch, when used, only
-provides device memory (a batch workspace) and the HIP stream."""
+of the search runs in the library's HIP kernels.
+
+One HIP runtime per process: libpms is built against the system ROCm, and
+the torch wheel bundles its own HIP runtime under the same soname, so a
+process that loads libpms must not also load torch's runtime.  Device memory
+comes from the library itself (or from a caller workspace pointer allocated
+in the same runtime); streams are passed as raw hipStream_t handles."""
 from __future__ import annotations
 
 import ctypes
@@ -53,6 +58,15 @@ class Tune(ctypes.Structure):
                          split, out_capacity)
 
 
+class Work(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "compat_pairs", "items", "pushes", "filter_words", "triple_tests", "tuples",
+        "gen_evals", "candidates", "verify_tests", "motifs_emitted")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 class _StreamConfig(ctypes.Structure):
     _fields_ = [("device_mem_cap", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("max_wave", ctypes.c_int32), ("tune", Tune)]
@@ -61,11 +75,27 @@ class _StreamConfig(ctypes.Structure):
 _lib = None
 
 
+def _foreign_hip_runtime() -> Optional[str]:
+    """Path of a HIP runtime other than the system one already mapped here."""
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line and "/opt/rocm" not in line:
+                    return line.split()[-1]
+    except OSError:
+        pass
+    return None
+
+
 def load():
     """Load libpms.so; raises if it has not been built (no CPU fallback)."""
     global _lib
     if _lib is not None:
         return _lib
+    other = _foreign_hip_runtime()
+    if other:
+        raise RuntimeError(f"another HIP runtime is already loaded ({other}); libpms needs the "
+                           "system ROCm runtime: load it in a process that does not import torch")
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1307_0571_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
@@ -82,6 +112,7 @@ def load():
     lib.pms_batch_results.argtypes = [vp, P(_Result)]
     lib.pms_batch_timings.argtypes = [vp, P(ctypes.c_float)]
     lib.pms_batch_destroy.argtypes = [vp]
+    lib.pms_batch_work.argtypes = [vp, ctypes.c_int32, P(Work)]
     lib.pms_stream_create.argtypes = [P(_StreamConfig), P(vp)]
     lib.pms_stream_submit.argtypes = [vp, P(_Instance), P(ctypes.c_uint64)]
     lib.pms_stream_poll.argtypes = [vp, ctypes.c_uint64, P(_Result)]
@@ -93,10 +124,13 @@ def load():
     lib.pms_strerror.restype = ctypes.c_char_p
     lib.pms_version.restype = ctypes.c_char_p
     lib.pms_default_threshold.argtypes = [ctypes.c_int] * 4
+    lib.pms_device_count.argtypes = [P(ctypes.c_int32)]
+    lib.pms_device_synchronize.argtypes = []
     for f in ("pms_solve", "pms_solve_batch", "pms_batch_create", "pms_batch_workspace_size",
               "pms_batch_run", "pms_batch_results", "pms_batch_timings", "pms_batch_destroy",
               "pms_stream_create", "pms_stream_submit", "pms_stream_poll", "pms_stream_wait",
-              "pms_stream_destroy", "pms_default_threshold"):
+              "pms_stream_destroy", "pms_default_threshold", "pms_batch_work",
+              "pms_device_count", "pms_device_synchronize"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -107,6 +141,16 @@ def strerror(status: int) -> str:
         return load().pms_strerror(int(status)).decode()
     except RuntimeError:
         return f"status {status}"
+
+
+def device_count() -> int:
+    n = ctypes.c_int32(0)
+    _check(load().pms_device_count(ctypes.byref(n)), "pms_device_count")
+    return int(n.value)
+
+
+def device_synchronize() -> None:
+    _check(load().pms_device_synchronize(), "pms_device_synchronize")
 
 
 def default_threshold(n: int, m: int, l: int, d: int) -> int:
@@ -160,11 +204,10 @@ def solve(seqs: Sequence[str], l: int, d: int, alphabet: str = "ACGT") -> List[s
 
 
 def _stream_ptr(stream) -> Optional[int]:
+    """A raw hipStream_t handle (int) or None for the library's own stream."""
     if stream is None:
         return None
-    if isinstance(stream, int):
-        return stream
-    return int(stream.cuda_stream)  # a torch.cuda.Stream
+    return int(stream)
 
 
 def solve_batch(problems: Sequence[Problem], tune: Optional[Tune] = None,
@@ -182,28 +225,29 @@ def solve_batch(problems: Sequence[Problem], tune: Optional[Tune] = None,
 class Batch:
     """Device-resident batch: inputs uploaded once, then run many times.
 
-    With ``torch_workspace=True`` the device memory is a torch uint8 tensor
-    (the library borrows it); otherwise the library allocates its own."""
+    ``workspace`` (optional) is a (device pointer, bytes) pair the library
+    borrows instead of allocating; ``Batch.workspace_size`` gives the size."""
 
     def __init__(self, problems: Sequence[Problem], tune: Optional[Tune] = None,
-                 torch_workspace: bool = False):
+                 workspace=None):
         lib = load()
         self.mar = _Marshal(problems)
         self.tune = tune
-        self.ws = None
-        ptr, size = None, 0
+        ptr, size = (None, 0) if workspace is None else (int(workspace[0]), int(workspace[1]))
         tp = ctypes.byref(tune) if tune else None
-        if torch_workspace:
-            import torch
-            sz = ctypes.c_size_t(0)
-            _check(lib.pms_batch_workspace_size(self.mar.arr, self.mar.count, tp,
-                                                ctypes.byref(sz)), "pms_batch_workspace_size")
-            self.ws = torch.empty(int(sz.value), dtype=torch.uint8, device="cuda")
-            ptr, size = self.ws.data_ptr(), int(sz.value)
         h = ctypes.c_void_p()
         _check(lib.pms_batch_create(self.mar.arr, self.mar.count, tp, ptr, size, ctypes.byref(h)),
                "pms_batch_create")
         self.h = h
+
+    @staticmethod
+    def workspace_size(problems: Sequence[Problem], tune: Optional[Tune] = None) -> int:
+        mar = _Marshal(problems)
+        sz = ctypes.c_size_t(0)
+        _check(load().pms_batch_workspace_size(mar.arr, mar.count,
+                                               ctypes.byref(tune) if tune else None,
+                                               ctypes.byref(sz)), "pms_batch_workspace_size")
+        return int(sz.value)
 
     def run(self, stream=None, graph: bool = False):
         _check(load().pms_batch_run(self.h, _stream_ptr(stream), int(graph)), "pms_batch_run")
@@ -217,6 +261,11 @@ class Batch:
         arr = (ctypes.c_float * 5)()
         _check(load().pms_batch_timings(self.h, arr), "pms_batch_timings")
         return list(arr)
+
+    def work(self, i: int = 0) -> dict:
+        w = Work()
+        _check(load().pms_batch_work(self.h, i, ctypes.byref(w)), "pms_batch_work")
+        return w.as_dict()
 
     def close(self):
         if getattr(self, "h", None):

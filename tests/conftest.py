@@ -14,11 +14,10 @@ def pytest_configure(config):
 
 
 def _gpu_present() -> bool:
-    try:
-        import torch
-        return torch.cuda.is_available()
-    except Exception:
-        return False
+    # no HIP call and no torch during collection: the GPU tests load libpms
+    # (system ROCm) themselves, and the torch wheel bundles a second HIP
+    # runtime under the same soname
+    return os.path.exists("/dev/kfd") and os.path.exists("/dev/dri")
 
 
 def pytest_collection_modifyitems(config, items):

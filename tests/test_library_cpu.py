@@ -1,0 +1,96 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function include/pms.h declares, and rejects invalid input before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1307_0571_amd import instances as I
+from paper_1307_0571_amd import pms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pms.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pms_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pms.LIB_PATH):
+        from paper_1307_0571_amd import build
+        build.build()
+    return pms.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    assert b"gfx950" in lib.pms_version()
+    for code in range(-8, 1):
+        assert pms.strerror(code)
+    assert pms.strerror(pms.PMS_E_ALPHABET).startswith("character")
+
+
+def _status(seqs, l, d, alphabet="ACGT", m=None):
+    lib = pms.load()
+    enc = [s.encode() for s in seqs]
+    arr = (ctypes.c_char_p * max(1, len(enc)))(*enc)
+    res = pms._Result()
+    mm = len(seqs[0]) if m is None else m
+    return lib.pms_solve(arr, len(seqs), mm, alphabet.encode(), l, d, ctypes.byref(res))
+
+
+def test_rejects_invalid_input(lib):
+    ok = ["ACGTACGT", "TTGACGTA"]
+    assert _status(ok, 4, 4) == pms.PMS_E_INVAL           # d >= l
+    assert _status(ok, 0, 0) == pms.PMS_E_INVAL           # l < 1
+    assert _status(ok, 4, -1) == pms.PMS_E_INVAL          # d < 0
+    assert _status(["ACGTACGT", "ACGTACG"], 4, 1, m=8) == pms.PMS_E_INVAL  # short string
+    assert _status(["ACGTACGT", "ACGTACGTA"], 4, 1, m=8) == pms.PMS_E_INVAL  # long string
+    assert _status(["ACGTNCGT", "ACGTACGT"], 4, 1) == pms.PMS_E_ALPHABET
+    assert _status(["acgtacgt", "ACGTACGT"], 4, 1) == pms.PMS_E_ALPHABET  # case-sensitive
+    assert _status(ok, 4, 1, alphabet="ACGA") == pms.PMS_E_ALPHABET      # repeated letter
+    assert _status(["ACGACGAC", "CCGAAGAC"], 4, 1, alphabet="ACG") == pms.PMS_E_UNSUPPORTED
+    assert _status(["A" * 80, "C" * 80], 65, 3) == pms.PMS_E_UNSUPPORTED   # l > 64
+    many = I.random_strings(1, 33, 20).seqs
+    assert _status(many, 5, 1) == pms.PMS_E_UNSUPPORTED                   # n > 32
+    long = I.random_strings(2, 2, 2100).seqs
+    assert _status(long, 10, 2) == pms.PMS_E_UNSUPPORTED                  # m - l + 1 > 2048
+
+
+def test_null_arguments(lib):
+    res = pms._Result()
+    assert lib.pms_solve(None, 1, 4, b"ACGT", 2, 0, ctypes.byref(res)) == pms.PMS_E_INVAL
+    arr = (ctypes.c_char_p * 1)(b"ACGT")
+    assert lib.pms_solve(arr, 1, 4, b"ACGT", 2, 0, None) == pms.PMS_E_INVAL
+    assert lib.pms_solve_batch(None, 1, None, None, None) == pms.PMS_E_INVAL
+    assert lib.pms_batch_destroy(None) == pms.PMS_OK
+
+
+def test_default_threshold_range(lib):
+    for (l, d) in [(9, 2), (11, 3), (13, 4), (15, 5), (17, 6), (19, 7), (50, 21)]:
+        t = pms.default_threshold(20, 600, l, d)
+        assert 2 <= t <= 8
+    # more windows per string -> never a larger threshold (Appendix D: t falls with m)
+    assert pms.default_threshold(20, 2000, 15, 5) <= pms.default_threshold(20, 300, 15, 5)
+
+
+def test_workspace_size_is_host_only(lib):
+    inst = I.planted(3, 9, 2, 10, 200)
+    mar = pms._Marshal([pms.Problem(inst.seqs, 9, 2)])
+    sz = ctypes.c_size_t(0)
+    assert lib.pms_batch_workspace_size(mar.arr, 1, None, ctypes.byref(sz)) == pms.PMS_OK
+    r = 200 - 9 + 1
+    # at least the compat bit-matrix: N * n * ceil(r/64) words
+    assert sz.value >= (10 * r) * 10 * ((r + 63) // 64) * 8
