@@ -85,6 +85,75 @@ def cpu_baseline(problems, budget_s: float = 20.0, threads: int = 16):
             "sample": "; ".join(desc) + " (time scaled by r / windows done)"}
 
 
+def run_batched(args, I, pms):
+    """The batched configuration: instances with (l,d) uniform from
+    {(11,3),(13,4),(15,5)}, n in [10,30], m in [300,1000], all solved by one
+    device pass (pms_batch) versus one pipeline run per instance (plain)."""
+    insts = I.batch_mix(1000, args.count)
+    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+    tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc)
+    b = pms.Batch(probs, tune=tune)
+    b.run()
+    b.results()  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+        res = b.results()
+    batched = (time.perf_counter() - t0) / args.steps
+    ph = b.timings()
+    b.close()
+    for x, r in zip(insts, res):
+        if x.motif not in r:
+            raise SystemExit(f"planted motif missing in batched instance seed {x.seed}")
+    plain = None
+    if not args.no_plain:
+        singles = [pms.Batch([p], tune=tune) for p in probs]
+        for sb in singles:
+            sb.run()
+            sb.results()
+        t0 = time.perf_counter()
+        for sb in singles:
+            sb.run()
+            sb.results()
+        plain = time.perf_counter() - t0
+        for sb in singles:
+            sb.close()
+    return {"batched_s": batched, "plain_s": plain, "phases_ms": ph,
+            "motifs": [len(r) for r in res]}
+
+
+def run_serving(args, I, pms, capacity_per_s):
+    """The serving configuration: Poisson arrivals at a fraction of the
+    measured batched capacity; (l,d) uniform from {(9,2),(11,3),(13,4),
+    (15,5),(17,6)}, n in [10,30], m in [200,1000]."""
+    import random
+    insts = I.batch_mix(2000, args.requests,
+                        ld=((9, 2), (11, 3), (13, 4), (15, 5), (17, 6)), m_range=(200, 1000))
+    rate = max(1e-3, args.load * capacity_per_s)
+    rng = random.Random(7)
+    srv = pms.Server()
+    sent = {}
+    t0 = time.perf_counter()
+    next_t = 0.0
+    for i, x in enumerate(insts):
+        next_t += rng.expovariate(rate)
+        now = time.perf_counter() - t0
+        if next_t > now:
+            time.sleep(next_t - now)
+        sent[srv.submit(pms.Problem(x.seqs, x.l, x.d))] = (time.perf_counter(), x)
+    lat = []
+    for tk, (ts, x) in sent.items():
+        r = srv.wait(tk)
+        lat.append(time.perf_counter() - ts)
+        if x.motif not in r:
+            raise SystemExit(f"planted motif missing in served request seed {x.seed}")
+    total = time.perf_counter() - t0
+    srv.close()
+    lat.sort()
+    return {"requests": len(insts), "offered_rate": rate, "instances_per_s": len(insts) / total,
+            "p50_ms": 1e3 * lat[len(lat) // 2], "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +161,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--workload", choices=["plain", "batched", "serving"], default="plain")
+    ap.add_argument("--wpc", type=int, default=0, help="persistent search waves per CU (0 = auto)")
+    ap.add_argument("--threshold", type=int, default=0, help="stack size t (0 = cost model)")
+    ap.add_argument("--count", type=int, default=256, help="instances in the batched workload")
+    ap.add_argument("--no-plain", action="store_true", help="batched: skip the per-instance runs")
+    ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: fraction of batched capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -100,13 +176,26 @@ def main():
     from paper_1307_0571_amd import instances as I
     from paper_1307_0571_amd import pms
 
+    if args.workload != "plain":
+        t0 = time.perf_counter()
+        b = run_batched(args, I, pms)
+        out = {"workload": "batched", "count": args.count, **b,
+               "batched_instances_per_s": args.count / b["batched_s"],
+               "plain_instances_per_s": (args.count / b["plain_s"]) if b["plain_s"] else None}
+        if args.workload == "serving":
+            out["serving"] = run_serving(args, I, pms, out["batched_instances_per_s"])
+        out["wall_s"] = time.perf_counter() - t0
+        print(json.dumps(out), flush=True)
+        return
+
+    tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc)
     seeds = [0, 1, 2, 3, 4]
     configs = [(13, 4), (15, 5)]
     batches = {}
     for s in seeds:
         for (l, d) in configs:
             inst = I.planted(s, l, d, 20, 600)
-            batches[(s, l)] = (pms.Batch([pms.Problem(inst.seqs, l, d)]), inst)
+            batches[(s, l)] = (pms.Batch([pms.Problem(inst.seqs, l, d)], tune=tune), inst)
 
     def step(k, timed_phases=None):
         s = seeds[k % len(seeds)]
@@ -132,26 +221,24 @@ def main():
     n_inst = args.steps * len(configs)
 
     # dominant kernel: the persistent search (HIP events on its stream);
-    # algorithmic work per launch from the oracle's unit counts (seed 0)
+    # algorithmic work per launch from the oracle's unit counts for the same
+    # instance at the same t
     units = load_units()
     search_ms = [p[2] for p in phases]
     compat_ms = [p[3] for p in phases]
     roofline = None
-    per_launch = []
-    for (l, d) in configs:
-        u = units.get((l, d, 0))
-        ms = [p[2] for p in phases if p[0] == (l, d) and p[1] == 0]
-        if u and ms:
-            per_launch.append((lane_ops(u), sum(ms) / len(ms)))
-    if per_launch:
-        ops = sum(o for o, _ in per_launch) / len(per_launch)
-        avg_ms = sum(m for _, m in per_launch) / len(per_launch)
+    t_of = {ld: args.threshold or pms.default_threshold(20, 600, *ld) for ld in configs}
+    counted = [(lane_ops(units[(ld[0], ld[1], s)]), ms) for (ld, s, ms, _, _) in phases
+               if (ld[0], ld[1], s) in units and units[(ld[0], ld[1], s)]["t"] == t_of[ld]]
+    if counted and len(counted) == len(phases):
+        ops = sum(o for o, _ in counted) / len(counted)
+        avg_ms = sum(search_ms) / len(search_ms)
         achieved = ops / (avg_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 5), "peak": round(PEAK_INT_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT_TOPS, 6), "traffic": None,
                     "kernel": "k_search", "avg_launch_ms": round(avg_ms, 4),
                     "algorithmic_lane_ops_per_launch": ops,
-                    "units": "oracle counts at the same t, seed 0 instances"}
+                    "units": "oracle work-unit counts of the same instances at the same t"}
     compat_pairs = sum(p[4] for p in phases)
     out = {
         "metric": "instances/s and Hd compares/s (mixed l,d), batched vs plain GPU, exact motif set",
@@ -169,7 +256,8 @@ def main():
         "config": {"workload": "plain GPU single instances (13,4) and (15,5), n=20, m=600, "
                                "exactly d substitutions per planted copy, seeds 0-4, "
                                "one instance per device pipeline run",
-                   "phases": "synchronised per phase"},
+                   "phases": "synchronised per phase",
+                   "waves_per_cu": args.wpc or 20, "threshold": args.threshold or "cost model"},
         "compat_hd_compares_per_s": round(compat_pairs / elapsed, 1),
         "compat_ms_avg": round(sum(compat_ms) / len(compat_ms), 4) if compat_ms else None,
         "roofline": roofline,

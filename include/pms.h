@@ -97,9 +97,11 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabe
               int32_t l, int32_t d, pms_result* out);
 
 /* Solve `count` instances of any mix of (l, d, n, m) in one device pass: one
- * pack launch, one compat launch, one persistent search launch fed by a
- * device work queue, one sort/unique launch.  outs[i] receives instance i's
- * set.  tune may be NULL. */
+ * pack launch, one compat launch, a persistent search fed by a device work
+ * queue (two launches: the level-2 work items, then the parts of items too
+ * large for one wave), one sort/unique launch.  outs[i] receives instance
+ * i's set.  tune may be NULL.  At most 2^21 instances per call
+ * (PMS_E_UNSUPPORTED beyond). */
 int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
                     const pms_tune* tune, void* hip_stream);
 

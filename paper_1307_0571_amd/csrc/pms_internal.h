@@ -15,6 +15,16 @@ constexpr int kVCap = 512;       // survivor l-mers staged in LDS for verificati
 constexpr int kCandCap = 128;    // candidate buffer in LDS
 constexpr int kNodeBatch = 16;   // generator nodes expanded per wave step (x4 children)
 constexpr int kNodeCap = 4 * kNodeBatch * kMaxL;  // node stack bound per wave (see search)
+constexpr int kRing = 128;       // top of the node stack kept in LDS (power of two, >= 128)
+constexpr int kSplitTuples = 8;  // third stack members one work item keeps (rest: part items)
+constexpr int kMaxInst = 1 << 21;  // instances per batch (21-bit field of a work item)
+
+// Work item (64 bits): inst << 43 | lo << 32 | u1 << 16 | p2 << 11 | x2.
+// u1: window of string 0 (level 1); p2, x2: string and window of the second
+// stack member (p2 == 0 marks n == 1); lo: first rank, among the survivors
+// of the string chosen at stack size 2, that the item covers (0 for the
+// items the expansion writes; part items cover kSplitTuples ranks from lo).
+constexpr uint64_t kNoItem = ~0ull;  // part slot that was reserved but not written
 
 // One instance as the kernels see it.
 struct InstDev {
@@ -78,15 +88,16 @@ struct DevBufs {
     void* lmers;
     uint64_t* compat;
     uint64_t* items;
+    uint64_t* parts;     // part items (second search launch)
     Node* nodes;
     uint64_t* keys;
     InstCounters* ctr;
-    QueueCounters* q;
+    QueueCounters* q;    // q[0]: items, q[1]: parts
 };
 
 // Kernel launchers (pms_kernels.hip).  All enqueue on `stream`.
 hipError_t launch_reset(const LaunchPlan& p, const DevBufs& b, unsigned long long item_cap,
-                        hipStream_t stream);
+                        unsigned long long part_cap, hipStream_t stream);
 hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 hipError_t launch_compat(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);

@@ -68,7 +68,8 @@ __device__ __forceinline__ int wave_min(int x) {
 
 // --------------------------------------------------------------- reset
 
-__global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigned long long item_cap) {
+__global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigned long long item_cap,
+                        unsigned long long part_cap) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_inst) {
         ctr[i].out_count = 0;
@@ -77,12 +78,21 @@ __global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigne
         ctr[i].pad = 0;
         ctr[i].items = 0;
     }
-    if (i == 0) {
-        q->item_count = 0;
-        q->item_next = 0;
-        q->item_cap = item_cap;
-        q->pad = 0;
+    if (i < 2) {
+        q[i].item_count = 0;
+        q[i].item_next = 0;
+        q[i].item_cap = i == 0 ? item_cap : part_cap;
+        q[i].pad = 0;
     }
+}
+
+// Part slots start as kNoItem: a slot reserved by a search wave that then
+// found the part queue full is skipped by the second search launch.
+__global__ void k_fill_parts(uint64_t* parts, unsigned long long n) {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride)
+        parts[i] = kNoItem;
 }
 
 // ---------------------------------------------------------------- pack (a1)
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
 // are exactly the compat row C[u1][j] (Algorithm 2's first push and filter).
 // Picks the smallest remaining string (ties: lowest index; Section 2.1) and
 // appends one work item per survivor u2 of that string.
-// Item layout: inst << 32 | u1 << 16 | p2 << 11 | x2; p2 = 0 (string 0 is
+// Items as pms_internal.h lays them out, with lo = 0; p2 = 0 (string 0 is
 // never a search row) marks n == 1, where the stack {u1} is already complete.
 
 __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ insts,
@@ -190,7 +200,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
         if (lane == 0) {
             unsigned long long at = atomicAdd(&q->item_count, 1ull);
             if (at < q->item_cap)
-                items[at] = ((uint64_t)inst << 32) | ((uint64_t)u1 << 16);
+                items[at] = ((uint64_t)inst << 43) | ((uint64_t)u1 << 16);
             else
                 atomicOr(&ctr[inst].flags, kFlagItemOverflow);
             atomicAdd(&ctr[inst].items, 1ull);
@@ -234,7 +244,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
             bits &= bits - 1;
             const uint64_t x2 = (uint64_t)(w * 64 + b);
             items[base + o++] =
-                ((uint64_t)inst << 32) | ((uint64_t)u1 << 16) | ((uint64_t)p2 << 11) | x2;
+                ((uint64_t)inst << 43) | ((uint64_t)u1 << 16) | ((uint64_t)p2 << 11) | x2;
         }
         done += __shfl(incl, 63, 64);
     }
@@ -250,10 +260,13 @@ struct SearchLds {
     Lm<W> st[TMAX];                  // the stack
     typename MaskOf<W>::type E[TMAX][TMAX];  // e(s_a, s_b) differing-position masks
     int HD[TMAX][TMAX];              // Hd(s_a, s_b)
+    typename MaskOf<W>::type rh[kRing], rl[kRing];  // generator node ring: prefix planes
+    uint8_t rd[kRing];                               // and depth
     Lm<W> cand[kCandCap];            // complete common neighbours awaiting the check
     Lm<W> vset[kVCap];               // staged survivors (verification)
-    uint16_t voff[kMaxN + 1];        // staged survivors of string j: [voff[j], voff[j+1])
-    int ncand;
+    uint16_t voff[kMaxN + 1];        // segment g of vset: [voff[g], voff[g+1])
+    uint16_t rowbase[kMaxN];         // first vset slot of string j's segment
+    int nseg;                        // staged segments (remaining strings)
     int item;
 };
 
@@ -366,6 +379,26 @@ struct Searcher {
         return v & 31;
     }
 
+    // window of the survivor of rank nth (0-based) of string p at level k,
+    // or -1 if the string has no more survivors; lanes hold one word each
+    // (bw <= 32)
+    __device__ int nth_bit(int k, int p, int nth) {
+        const uint64_t* row = level(k) + p * I.bw;
+        const uint64_t w = lane < I.bw ? row[lane] : 0ull;
+        const int c = pc(w);
+        const int incl = wave_incl_scan(c);
+        const unsigned long long m = ballot(incl - c <= nth && nth < incl);
+        if (m == 0ull) return -1;
+        const int src = __builtin_ctzll(m);
+        int res = -1;
+        if (lane == src) {
+            uint64_t x = w;
+            for (int i = incl - c; i < nth; i++) x &= x - 1;
+            res = lane * 64 + __builtin_ctzll(x);
+        }
+        return __shfl(res, src, 64);
+    }
+
     // next survivor of string p at level k with window >= from, or -1
     __device__ int next_bit(int k, int p, int from) {
         const uint64_t* row = level(k) + p * I.bw;
@@ -392,69 +425,120 @@ struct Searcher {
     }
 
     // Check candidates cand[0..nc) against every remaining string of level k
-    // (Algorithm 2's isMotif on the filtered rows); lane c checks candidate c.
+    // (Algorithm 2's isMotif on the filtered rows).
+    //
+    // Staged survivors: one string segment at a time, fewest survivors first,
+    // over the candidates still alive.  With A alive candidates padded to a
+    // power of two Ap, lane (sub, c) tests candidate c against survivors
+    // sub, sub + 64/Ap, ... of the segment; a wave ballot folded over the
+    // replicas gives which candidates have a survivor within d.  Those are
+    // compacted to the front of cand and the rest are dropped, so a segment
+    // costs ceil(size * Ap / 64) steps.  Unstaged (too many survivors for
+    // LDS): lane c checks candidate c against the level bitsets.
     __device__ void verify(int k, int nc, bool staged) {
+        const int d = I.d;
+        if (staged) {
+            int A = nc;
+            const int R = S.nseg;
+            for (int g = 0; g < R && A > 0; g++) {
+                const int a = S.voff[g], e = S.voff[g + 1];
+                const int lg = A > 32 ? 6 : A > 16 ? 5 : A > 8 ? 4 : A > 4 ? 3 : A > 2 ? 2 : A > 1 ? 1 : 0;
+                const int Ap = 1 << lg, P = 64 >> lg;
+                const int ci = lane & (Ap - 1), sub = lane >> lg;
+                const bool vc = ci < A;
+                const Lm<W> mv = S.cand[vc ? ci : 0];
+                bool hit = false;
+                if (vc)
+                    for (int q = a + sub; q < e; q += P) hit |= pc(dmask(mv, S.vset[q])) <= d;
+                uint64_t m = ballot(hit);
+                for (int sh = 32; sh >= Ap; sh >>= 1) m |= m >> sh;
+                const uint64_t found = m & (A >= 64 ? ~0ull : ((1ull << A) - 1ull));
+                const bool keep = lane < A && ((found >> lane) & 1ull);
+                const Lm<W> mk = S.cand[lane < A ? lane : 0];
+                __syncthreads();
+                if (keep) S.cand[rank_below(found)] = mk;
+                __syncthreads();
+                A = __popcll(found);
+            }
+            if (lane < A) emit(S.cand[lane]);
+            __syncthreads();
+            return;
+        }
         const Lm<W> mv = S.cand[lane < nc ? lane : 0];
         bool ok = lane < nc;
         const uint32_t rows = S.rows[k];
-        const int d = I.d;
         for (int j = 0; j < I.n; j++) {
             if (!((rows >> j) & 1u)) continue;
             if (ballot(ok) == 0ull) break;
             bool found = false;
-            if (staged) {
-                const int a = S.voff[j], e = S.voff[j + 1];
-                for (int q = a; q < e; q++) {
-                    found |= pc(dmask(mv, S.vset[q])) <= d;
-                    if (((q - a) & 7) == 7 && ballot(ok && !found) == 0ull) break;
+            const uint64_t* row = level(k) + j * I.bw;
+            for (int w = 0; w < I.bw; w++) {
+                uint64_t bits = row[w];
+                while (bits) {
+                    const int b = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    found |= pc(dmask(mv, L[j * I.r + w * 64 + b])) <= d;
                 }
-            } else {
-                const uint64_t* row = level(k) + j * I.bw;
-                for (int w = 0; w < I.bw; w++) {
-                    uint64_t bits = row[w];
-                    while (bits) {
-                        const int b = __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        found |= pc(dmask(mv, L[j * I.r + w * 64 + b])) <= d;
-                    }
-                    if (ballot(ok && !found) == 0ull) break;
-                }
+                if (ballot(ok && !found) == 0ull) break;
             }
             ok &= found;
         }
         if (ok) emit(mv);
     }
 
-    // Stage the survivors of level k (in string order) into LDS if they fit.
+    // Stage the survivors of level k into LDS if they fit: one segment per
+    // remaining string, segments ordered by survivor count (ties: lower
+    // string first), so the check meets the most selective strings first.
     __device__ bool stage(int k) {
+        const int n = I.n;
         const uint32_t rows = S.rows[k];
-        int tot = 0;
-        for (int j = 0; j < I.n; j++) tot += ((rows >> j) & 1u) ? (int)cnt16(k, j) : 0;
+        const bool mine = lane < n && ((rows >> lane) & 1u);
+        const int c = mine ? (int)cnt16(k, lane) : 0;
+        const int incl = wave_incl_scan(c);
+        const int tot = __shfl(incl, 63, 64);
         if (tot > kVCap) return false;
-        if (lane == 0) {
-            int acc = 0;
-            for (int j = 0; j <= I.n; j++) {
-                S.voff[j] = (uint16_t)acc;
-                if (j < I.n && ((rows >> j) & 1u)) acc += (int)cnt16(k, j);
-            }
+        // rank of this string among the remaining ones by (count, index)
+        int rank = 0;
+        for (int j = 0; j < n; j++) {
+            const int cj = __shfl(c, j, 64);
+            const bool in = (rows >> j) & 1u;
+            rank += (in && (cj < c || (cj == c && j < lane))) ? 1 : 0;
         }
+        // segment starts: prefix sum of the counts in rank order
+        const unsigned long long inm = ballot(mine);
+        const int R = __popcll(inm);
+        if (mine) S.voff[rank] = (uint16_t)c;  // count, turned into a start below
+        __syncthreads();
+        const int cr = lane < R ? (int)S.voff[lane] : 0;
+        const int ir = wave_incl_scan(cr);
+        __syncthreads();
+        if (lane < R) S.voff[lane] = (uint16_t)(ir - cr);
+        if (lane == 0) {
+            S.voff[R] = (uint16_t)tot;
+            S.nseg = R;
+        }
+        __syncthreads();
+        if (mine) S.rowbase[lane] = S.voff[rank];
+        const int natural = incl - c;  // start of this string in index order
+        __syncthreads();
         const uint64_t* lvk = level(k);
-        const int total = I.n * I.bw;
+        const int total = n * I.bw;
         int done = 0;
         for (int i0 = 0; i0 < total; i0 += 64) {
             const int i = i0 + lane;
             const int j = i / I.bw;
             uint64_t bits = (i < total && ((rows >> j) & 1u)) ? lvk[i] : 0ull;
-            const int c = pc(bits);
-            const int incl = wave_incl_scan(c);
-            int o = done + incl - c;
+            const int cb = pc(bits);
+            const int inc = wave_incl_scan(cb);
+            const int nat_j = __shfl(natural, j < 64 ? j : 0, 64);
+            int o = (int)S.rowbase[j < kMaxN ? j : 0] + (done + inc - cb - nat_j);
             const int w = i - j * I.bw;
             while (bits) {
                 const int b = __builtin_ctzll(bits);
                 bits &= bits - 1;
                 S.vset[o++] = L[j * I.r + w * 64 + b];
             }
-            done += __shfl(incl, 63, 64);
+            done += __shfl(inc, 63, 64);
         }
         __syncthreads();
         return true;
@@ -464,36 +548,51 @@ struct Searcher {
     // budgets, by the pair condition on suffixes (Hd > r_i + r_j) and by
     // Theorem 1 on suffixes of every triple (Cd > r_i + r_j + r_q); a leaf is
     // reported only with every budget >= 0.  Wave-parallel: each step pops up
-    // to 16 nodes from the top of this wave's stack and lanes evaluate their
-    // 4 children; surviving internal children are pushed (ballot + prefix
-    // sum), complete l-mers go to the candidate buffer.
+    // to 16 nodes from the top of the node stack and lanes evaluate their 4
+    // children; surviving internal children are pushed (ballot + prefix
+    // sum), complete l-mers go to the candidate buffer.  A node is its prefix
+    // (bit-planes of positions < depth) and its depth; the budgets are
+    // recomputed from the prefix.  The stack's top kRing entries live in an
+    // LDS ring; older entries move to this wave's global node area in blocks
+    // of 64 when the ring fills and come back when pops reach them.
     __device__ void generate(int k) {
         const bool staged = stage(k);
-        Lm<W> s[TMAX];
-        M e[TMAX][TMAX];
+        switch (k) {
+            case 1: gen_tree<1>(staged); break;
+            case 2: gen_tree<2>(staged); break;
+            case 3: if constexpr (TMAX >= 3) gen_tree<3>(staged); break;
+            case 4: if constexpr (TMAX >= 4) gen_tree<4>(staged); break;
+            case 5: if constexpr (TMAX >= 5) gen_tree<5>(staged); break;
+            case 6: if constexpr (TMAX >= 6) gen_tree<6>(staged); break;
+            case 7: if constexpr (TMAX >= 7) gen_tree<7>(staged); break;
+            case 8: if constexpr (TMAX >= 8) gen_tree<8>(staged); break;
+            default: break;
+        }
+    }
+
+    // The tree for a stack of exactly K members (K known at compile time,
+    // so every per-member test is unrolled and evaluated without branches).
+    template <int K>
+    __device__ void gen_tree(bool staged) {
+        const int k = K;
+        Lm<W> s[K];
+        M e[K][K];
 #pragma unroll
-        for (int a = 0; a < TMAX; a++) {
-            s[a] = S.st[a < k ? a : 0];
+        for (int a = 0; a < K; a++) {
+            s[a] = S.st[a];
 #pragma unroll
-            for (int b = 0; b < TMAX; b++) e[a][b] = (a < b && b < k) ? S.E[a][b] : (M)0;
+            for (int b = 0; b < K; b++) e[a][b] = (a < b) ? S.E[a][b] : (M)0;
         }
         const int l = I.l, d = I.d;
-        uint64_t bud0 = 0;
-#pragma unroll
-        for (int a = 0; a < TMAX; a++)
-            if (a < k) bud0 |= (uint64_t)d << (8 * a);
         if (lane == 0) {
-            Node rt;
-            rt.h = 0;
-            rt.lo = 0;
-            rt.bud = bud0;
-            rt.depth = 0;
-            rt.pad = 0;
-            nodes[0] = rt;
-            S.ncand = 0;
+            S.rh[0] = 0;
+            S.rl[0] = 0;
+            S.rd[0] = 0;
         }
         __syncthreads();
-        int size = 1;
+        int size = 1;  // stack entries
+        int g = 0;     // entries [0, g) are in the global node area, [g, size) in the ring
+        int nc = 0;    // candidates waiting in S.cand
         while (size > 0) {
             if (size > kNodeCap - 4 * kNodeBatch) {
                 // cannot happen (each depth holds at most one batch of 4*16
@@ -503,81 +602,87 @@ struct Searcher {
             }
             const int B = size < kNodeBatch ? size : kNodeBatch;
             const int base = size - B;
+            if (base < g) {
+                // bring back the block of 64 below the ring (the ring then
+                // holds fewer than 16 + 64 entries, so no slot is live twice)
+                g -= 64;
+                const Node x = nodes[g + lane];
+                const int sl = (g + lane) & (kRing - 1);
+                S.rh[sl] = (M)x.h;
+                S.rl[sl] = (M)x.lo;
+                S.rd[sl] = (uint8_t)x.depth;
+                __syncthreads();
+            }
             const int ni = lane >> 2;
             const int alpha = lane & 3;
             const bool active = ni < B;
-            Node nd;
-            if (active) nd = nodes[base + ni];
-            else {
-                nd.h = 0;
-                nd.lo = 0;
-                nd.bud = 0;
-                nd.depth = 0;
-            }
+            const int rs = (base + (active ? ni : 0)) & (kRing - 1);
+            const M nh = S.rh[rs];
+            const M nl = S.rl[rs];
+            const int p = (int)S.rd[rs];
             __syncthreads();  // every lane has read its node before pushes overwrite
             size = base;
-            const int p = (int)nd.depth;
-            bool valid = active;
-            int rb[TMAX];
-            uint64_t nbud = 0;
-#pragma unroll
-            for (int a = 0; a < TMAX; a++) {
-                if (a < k) {
-                    const int ca = (int)((((uint64_t)s[a].h >> p) & 1ull) << 1 | (((uint64_t)s[a].lo >> p) & 1ull));
-                    int ra = (int)((nd.bud >> (8 * a)) & 0xFFull) - (ca != alpha ? 1 : 0);
-                    rb[a] = ra;
-                    valid &= ra >= 0;
-                    nbud |= (uint64_t)(ra < 0 ? 0 : ra) << (8 * a);
-                } else {
-                    rb[a] = 0;
-                }
-            }
+            const M below = p >= 8 * (int)sizeof(M) ? ~(M)0 : (((M)1 << p) - (M)1);
             const int sfx = p + 1;
-            if (valid) {
+            bool valid = active;
+            int rb[K];
 #pragma unroll
-                for (int a = 0; a < TMAX; a++)
-#pragma unroll
-                    for (int b = a + 1; b < TMAX; b++)
-                        if (b < k) valid &= pc(suf(e[a][b], sfx)) <= rb[a] + rb[b];
+            for (int a = 0; a < K; a++) {
+                const M da = ((nh ^ s[a].h) | (nl ^ s[a].lo)) & below;
+                const int ca = (int)((((uint64_t)s[a].h >> p) & 1ull) << 1 | (((uint64_t)s[a].lo >> p) & 1ull));
+                rb[a] = d - pc(da) - (ca != alpha ? 1 : 0);
+                valid &= rb[a] >= 0;
             }
-            if (valid) {
 #pragma unroll
-                for (int a = 0; a < TMAX; a++)
+            for (int a = 0; a < K; a++)
 #pragma unroll
-                    for (int b = a + 1; b < TMAX; b++)
+                for (int b = a + 1; b < K; b++) valid &= pc(suf(e[a][b], sfx)) <= rb[a] + rb[b];
 #pragma unroll
-                        for (int c = b + 1; c < TMAX; c++)
-                            if (c < k) {
-                                const M u = suf((M)(e[a][b] | e[a][c]), sfx);
-                                const M x = suf((M)(e[a][b] & e[a][c] & e[b][c]), sfx);
-                                valid &= pc(u) + pc(x) <= rb[a] + rb[b] + rb[c];
-                            }
-            }
-            const uint64_t ch = nd.h | ((uint64_t)(alpha >> 1) << p);
-            const uint64_t cl = nd.lo | ((uint64_t)(alpha & 1) << p);
+            for (int a = 0; a < K; a++)
+#pragma unroll
+                for (int b = a + 1; b < K; b++)
+#pragma unroll
+                    for (int c = b + 1; c < K; c++) {
+                        const M u = suf((M)(e[a][b] | e[a][c]), sfx);
+                        const M x = suf((M)(e[a][b] & e[a][c] & e[b][c]), sfx);
+                        valid &= pc(u) + pc(x) <= rb[a] + rb[b] + rb[c];
+                    }
+            const M ch = nh | ((M)(alpha >> 1) << p);
+            const M cl = nl | ((M)(alpha & 1) << p);
             const bool leaf = valid && sfx == l;
             const bool push = valid && sfx < l;
             const unsigned long long pm = ballot(push);
-            if (push) {
-                Node c;
-                c.h = ch;
-                c.lo = cl;
-                c.bud = nbud;
-                c.depth = (uint32_t)sfx;
-                c.pad = 0;
-                nodes[size + rank_below(pm)] = c;
+            const int npush = __popcll(pm);
+            if (size + npush - g > kRing) {
+                // move the oldest 64 ring entries to the global node area
+                // (the ring holds more than kRing - 64 >= 64 of them)
+                const int sl = (g + lane) & (kRing - 1);
+                Node x;
+                x.h = (uint64_t)S.rh[sl];
+                x.lo = (uint64_t)S.rl[sl];
+                x.bud = 0;
+                x.depth = (uint32_t)S.rd[sl];
+                x.pad = 0;
+                nodes[g + lane] = x;
+                g += 64;
+                __syncthreads();  // spilled slots read before the pushes reuse them
             }
-            size += __popcll(pm);
+            if (push) {
+                const int sl = (size + rank_below(pm)) & (kRing - 1);
+                S.rh[sl] = ch;
+                S.rl[sl] = cl;
+                S.rd[sl] = (uint8_t)sfx;
+            }
+            size += npush;
             const unsigned long long lm = ballot(leaf);
-            const int nc0 = S.ncand;
             if (leaf) {
                 Lm<W> mv;
-                mv.h = (typename MaskOf<W>::type)ch;
-                mv.lo = (typename MaskOf<W>::type)cl;
-                S.cand[nc0 + rank_below(lm)] = mv;
+                mv.h = ch;
+                mv.lo = cl;
+                S.cand[nc + rank_below(lm)] = mv;
             }
+            nc += __popcll(lm);
             __syncthreads();
-            int nc = nc0 + __popcll(lm);
             if (nc >= 64) {
                 verify(k, 64, staged);
                 __syncthreads();
@@ -586,31 +691,39 @@ struct Searcher {
                 __syncthreads();
                 if (lane < rest) S.cand[lane] = mv;
                 nc = rest;
+                __syncthreads();
             }
-            if (lane == 0) S.ncand = nc;
-            __syncthreads();
         }
-        const int nc = S.ncand;
         if (nc > 0) verify(k, nc, staged);
         __syncthreads();
     }
 };
 
+// Persistent search over one queue.  phase 0 takes the expansion's items;
+// when the string chosen at stack size 2 has more than kSplitTuples
+// survivors, the wave keeps ranks [0, kSplitTuples) and appends part items
+// for the rest to the part queue, which phase 0 never reads.  phase 1 (a
+// second launch after phase 0 has finished) takes the part items.  Every
+// wave leaves when its queue is empty; nothing waits on another wave.
 template <int W, int TMAX>
 __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts,
                                                const Lm<W>* __restrict__ lmers,
                                                const uint64_t* __restrict__ compat,
                                                const uint64_t* __restrict__ items,
-                                               QueueCounters* __restrict__ q,
+                                               uint64_t* __restrict__ parts,
+                                               QueueCounters* __restrict__ qs,
                                                Node* __restrict__ node_scratch,
                                                uint64_t* __restrict__ keys,
                                                InstCounters* __restrict__ ctr,
-                                               int level_words) {
+                                               int level_words, int phase) {
     extern __shared__ uint64_t dyn[];
     __shared__ SearchLds<W, TMAX> S;
     __shared__ unsigned cntw[(TMAX + 1) * kMaxN];
     const int lane = lane_id();
     Node* nodes = node_scratch + (int64_t)blockIdx.x * kNodeCap;
+    QueueCounters* q = qs + phase;
+    QueueCounters* qp = qs + 1;
+    const uint64_t* src = phase == 0 ? items : parts;
     for (;;) {
         if (lane == 0) {
             unsigned long long it = atomicAdd(&q->item_next, 1ull);
@@ -620,8 +733,10 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         const int it = uni(S.item);
         __syncthreads();
         if (it < 0) break;
-        const uint64_t item = items[it];
-        const int inst = uni((int)(item >> 32));
+        const uint64_t item = src[it];
+        if (item == kNoItem) continue;
+        const int inst = uni((int)(item >> 43));
+        const int lo = uni((int)((item >> 32) & 0x7FF));
         const int u1 = uni((int)((item >> 16) & 0xFFFF));
         const int p2 = uni((int)((item >> 11) & 31));
         const int x2 = uni((int)(item & 0x7FF));
@@ -644,6 +759,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         if (!sr.push_filter(1, p2, x2)) continue;
         int k = 2;
         bool descend = true;
+        int rank2 = 0, rank2_end = 0x7FFFFFFF;  // survivor ranks this item covers at k == 2
         for (;;) {
             if (descend) {
                 if (k >= t || S.rows[k] == 0u) {
@@ -654,14 +770,40 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                     continue;
                 }
                 const int p = uni(sr.choose_row(k));
+                int cur = 0;
+                if (k == 2) {
+                    const int c = uni((int)sr.cnt16(2, p));
+                    if (phase == 0) {
+                        if (c > kSplitTuples) {
+                            const int extra = (c - 1) / kSplitTuples;
+                            unsigned long long base = 0;
+                            if (lane == 0) base = atomicAdd(&qp->item_count, (unsigned long long)extra);
+                            base = __shfl(base, 0, 64);
+                            if (base + (unsigned long long)extra <= qp->item_cap) {
+                                for (int e = lane; e < extra; e += 64)
+                                    parts[base + e] = item | ((uint64_t)((e + 1) * kSplitTuples) << 32);
+                                rank2_end = kSplitTuples;
+                            }
+                        }
+                    } else {
+                        rank2 = lo;
+                        rank2_end = lo + kSplitTuples;
+                        cur = uni(sr.nth_bit(2, p, lo));
+                        if (cur < 0) cur = 64 * I.bw;
+                    }
+                }
                 if (lane == 0) {
                     S.prow[k] = p;
-                    S.cursor[k] = 0;
+                    S.cursor[k] = cur;
                 }
                 __syncthreads();
             }
             const int p = uni(S.prow[k]);
-            const int x = uni(sr.next_bit(k, p, S.cursor[k]));
+            int x = uni(sr.next_bit(k, p, S.cursor[k]));
+            if (k == 2 && x >= 0) {
+                if (rank2 >= rank2_end) x = -1;
+                else rank2++;
+            }
             __syncthreads();
             if (x < 0) {
                 k--;
@@ -813,10 +955,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const InstDev* __restrict
 // ------------------------------------------------------------- launchers
 
 hipError_t launch_reset(const LaunchPlan& p, const DevBufs& b, unsigned long long item_cap,
-                        hipStream_t stream) {
+                        unsigned long long part_cap, hipStream_t stream) {
     int blocks = (p.n_inst + 255) / 256;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, stream, b.ctr, p.n_inst, b.q, item_cap);
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, stream, b.ctr, p.n_inst, b.q, item_cap,
+                       part_cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_parts, dim3(1024), dim3(256), 0, stream, b.parts, part_cap);
     return hipGetLastError();
 }
 
@@ -861,10 +1007,14 @@ size_t search_lds_bytes(const LaunchPlan& p) {
 template <int W, int TMAX>
 static hipError_t search_t(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
     const size_t lds = search_lds_bytes(p);
-    hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
-                       (const Lm<W>*)b.lmers, b.compat, b.items, b.q, b.nodes, b.keys, b.ctr,
-                       p.level_words);
-    return hipGetLastError();
+    for (int phase = 0; phase < 2; phase++) {
+        hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
+                           (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.q, b.nodes, b.keys,
+                           b.ctr, p.level_words, phase);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int W>

@@ -54,8 +54,10 @@ double ball_size(int l, int d) {
 
 // Stack size t at which the search switches to generation: minimise the
 // Appendix D cost model Time_s(t) + Time_p(t) over t, with p = N_2d / 4^l and
-// q = N_d / N_2d, then move one level deeper (generation and candidate checks
-// are the less regular part on a wavefront), clamped to [2, 8].
+// q = N_d / N_2d.  On the device a stack of three is never worse than two
+// once the model asks for more than one level (Theorem 1 makes the
+// three-l-mer tree free of dead ends), measured on MI355X for (9,2) .. (17,6);
+// the result is clamped to [2, 8].
 extern "C" int pms_default_threshold(int n, int m, int l, int d) {
     const int r = m - l + 1;
     if (r <= 0 || n <= 1) return 2;
@@ -73,7 +75,8 @@ extern "C" int pms_default_threshold(int n, int m, int l, int d) {
             best = t;
         }
     }
-    return std::max(2, std::min(kMaxT, best + 1));
+    const int t = best <= 1 ? 2 : std::max(3, best);
+    return std::max(2, std::min(kMaxT, t));
 }
 
 namespace {
@@ -166,6 +169,7 @@ struct pms_batch {
     void* ext_ws = nullptr;
     size_t ext_ws_bytes = 0;
     unsigned long long item_cap = 0;
+    unsigned long long part_cap = 0;
     pms_tune tune{};
     hipStream_t own_stream = nullptr;
     hipStream_t last = nullptr;
@@ -225,7 +229,9 @@ size_t plan_layout(pms_batch* bt) {
         p.tmax = std::max(p.tmax, d.t);
     }
     bt->item_cap = std::max<unsigned long long>(items, 1);
-    const int wpc = bt->tune.waves_per_cu > 0 ? bt->tune.waves_per_cu : 8;
+    // part items: a full part queue only makes waves keep their whole item
+    bt->part_cap = std::max<unsigned long long>(std::min<unsigned long long>(items, 1ull << 22), 1024);
+    const int wpc = bt->tune.waves_per_cu > 0 ? bt->tune.waves_per_cu : 20;
     p.search_blocks = device_cus() * wpc;
     p.compat_kernel = 1;
     const int64_t lmer_bytes = bt->words == 1 ? 8 : 16;
@@ -241,10 +247,11 @@ size_t plan_layout(pms_batch* bt) {
     size_t o_lmers = take(lmer_off * lmer_bytes);
     size_t o_compat = take(compat_off * 8);
     size_t o_items = take((int64_t)bt->item_cap * 8);
+    size_t o_parts = take((int64_t)bt->part_cap * 8);
     size_t o_nodes = take((int64_t)p.search_blocks * kNodeCap * (int64_t)sizeof(Node));
     size_t o_keys = take(out_off * 8 * bt->words);
     size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
-    size_t o_q = take(sizeof(QueueCounters));
+    size_t o_q = take(2 * sizeof(QueueCounters));
     // offsets are stored relative to the arena; resolve later
     bt->b.inst = (InstDev*)o_inst;
     bt->b.chars = (uint8_t*)o_chars;
@@ -252,6 +259,7 @@ size_t plan_layout(pms_batch* bt) {
     bt->b.lmers = (void*)o_lmers;
     bt->b.compat = (uint64_t*)o_compat;
     bt->b.items = (uint64_t*)o_items;
+    bt->b.parts = (uint64_t*)o_parts;
     bt->b.nodes = (Node*)o_nodes;
     bt->b.keys = (uint64_t*)o_keys;
     bt->b.ctr = (InstCounters*)o_ctr;
@@ -267,6 +275,7 @@ void resolve(pms_batch* bt) {
     bt->b.lmers = (void*)(a + (size_t)bt->b.lmers);
     bt->b.compat = (uint64_t*)(a + (size_t)bt->b.compat);
     bt->b.items = (uint64_t*)(a + (size_t)bt->b.items);
+    bt->b.parts = (uint64_t*)(a + (size_t)bt->b.parts);
     bt->b.nodes = (Node*)(a + (size_t)bt->b.nodes);
     bt->b.keys = (uint64_t*)(a + (size_t)bt->b.keys);
     bt->b.ctr = (InstCounters*)(a + (size_t)bt->b.ctr);
@@ -340,7 +349,7 @@ int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
     };
     rec(0);
     bool ok = true;
-    if (ok) { e = launch_reset(bt->plan, bt->b, bt->item_cap, s); ok = done(); }
+    if (ok) { e = launch_reset(bt->plan, bt->b, bt->item_cap, bt->part_cap, s); ok = done(); }
     if (ok) { e = launch_pack(bt->plan, bt->b, s); ok = done(); }
     rec(1);
     if (ok) { e = launch_compat(bt->plan, bt->b, s); ok = done(); }
@@ -361,6 +370,7 @@ int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
 
 int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pms_batch** out) {
     if (!out || count < 0 || (count > 0 && !inst)) return PMS_E_INVAL;
+    if (count > kMaxInst) return PMS_E_UNSUPPORTED;
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
     if (tune) bt->tune = *tune;

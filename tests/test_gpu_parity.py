@@ -132,3 +132,40 @@ def test_caller_workspace():
     finally:
         owner.close()
     assert size > 0
+
+
+def test_serving_matches_alone():
+    _say("serving: continuous batching, each result equals the instance alone")
+    insts = I.batch_mix(2000, 12, ld=((9, 2), (10, 2), (11, 3)), n_range=(5, 12),
+                        m_range=(100, 300))
+    srv = pms.Server(max_wave=4)
+    try:
+        tickets = [srv.submit(pms.Problem(x.seqs, x.l, x.d)) for x in insts]
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for x, g in zip(insts, got):
+        assert g == oracle.solve_b(x.seqs, x.l, x.d)
+        assert g == _gpu(x)
+
+
+def test_serving_admission_and_errors():
+    _say("serving: admission by device memory, invalid requests, poll")
+    inst = I.planted(3, 9, 2, 8, 150)
+    srv = pms.Server(device_mem_cap=1 << 20)  # 1 MiB: smaller than any instance's plan
+    try:
+        with pytest.raises(pms.PmsError) as e:
+            srv.submit(pms.Problem(inst.seqs, 9, 2))
+        assert e.value.status == pms.PMS_E_NOMEM
+        with pytest.raises(pms.PmsError) as e:
+            srv.submit(pms.Problem(inst.seqs, 9, 9))
+        assert e.value.status == pms.PMS_E_INVAL
+    finally:
+        srv.close()
+    srv = pms.Server()
+    try:
+        t = srv.submit(pms.Problem(inst.seqs, 9, 2))
+        got = srv.wait(t)
+        assert got == oracle.solve_a(inst.seqs, 9, 2)
+    finally:
+        srv.close()
