@@ -75,8 +75,8 @@ typedef struct {
 } pms_result;
 
 /* Search parameters.  Zero / negative fields mean "choose automatically".
- * None of them changes the result set (the method is exact for every
- * setting); they change only speed and memory. */
+ * None of them except s1_begin / s1_end changes the result set (the method
+ * is exact for every setting); they change only speed and memory. */
 typedef struct {
     int32_t threshold;      /* stack size t at which the search switches to
                                neighbourhood generation (Section 2.2,
@@ -86,9 +86,19 @@ typedef struct {
     int32_t triple_filter;  /* >= 0: filter survivors with Theorem 1 (default),
                                < 0: pairwise 2d filter only */
     int32_t waves_per_cu;   /* resident search waves per CU (persistent grid); 0 = auto */
-    int32_t compat_kernel;  /* 1: VALU xor/popcount, 2: int8 one-hot MFMA; 0 = auto */
-    int32_t split;          /* work-item depth: 2 (stack prefixes of two l-mers) or
-                               3 (three); 0 = auto */
+    int32_t compat_kernel;  /* 1: VALU xor/popcount (the only builder in this
+                               version; 2, an int8 one-hot MFMA builder, returns
+                               PMS_E_UNSUPPORTED); 0 = 1 */
+    int32_t split;          /* candidates for the third stack member one work
+                               item keeps; the rest become part items of this
+                               many each, searched by a second launch (1..2047;
+                               0 = 8) */
+    int32_t s1_begin;       /* search only the S_1 windows [s1_begin, s1_end) */
+    int32_t s1_end;         /* (Section 2.3's independent sub-problems).  The
+                               result is then the motifs that are within d of
+                               one of those windows.  0, 0 = every window;
+                               end beyond the last window is clamped;
+                               begin > end (end > 0) is PMS_E_INVAL */
     int64_t out_capacity;   /* initial motif slots per instance (pre-dedup); 0 = auto */
 } pms_tune;
 

@@ -16,14 +16,14 @@ constexpr int kCandCap = 128;    // candidate buffer in LDS
 constexpr int kNodeBatch = 16;   // generator nodes expanded per wave step (x4 children)
 constexpr int kNodeCap = 4 * kNodeBatch * kMaxL;  // node stack bound per wave (see search)
 constexpr int kRing = 128;       // top of the node stack kept in LDS (power of two, >= 128)
-constexpr int kSplitTuples = 8;  // third stack members one work item keeps (rest: part items)
+constexpr int kSplitDefault = 8;  // third stack members one work item keeps (rest: part items)
 constexpr int kMaxInst = 1 << 21;  // instances per batch (21-bit field of a work item)
 
 // Work item (64 bits): inst << 43 | lo << 32 | u1 << 16 | p2 << 11 | x2.
 // u1: window of string 0 (level 1); p2, x2: string and window of the second
 // stack member (p2 == 0 marks n == 1); lo: first rank, among the survivors
 // of the string chosen at stack size 2, that the item covers (0 for the
-// items the expansion writes; part items cover kSplitTuples ranks from lo).
+// items the expansion writes; part items cover `split` ranks from lo).
 constexpr uint64_t kNoItem = ~0ull;  // part slot that was reserved but not written
 
 // One instance as the kernels see it.
@@ -33,6 +33,7 @@ struct InstDev {
     int32_t bw;       // 64-bit words per row bitset, ceil(r / 64)
     int32_t t;        // stack size at which neighbourhood generation starts
     int32_t triple;   // Theorem 1 survivor filter on/off
+    int32_t s1_lo, s1_hi;  // S_1 windows searched: [s1_lo, s1_hi)
     int64_t chars_off;   // byte offset of the n*m characters
     int64_t lmer_off;    // l-mer offset (units of one packed l-mer)
     int64_t compat_off;  // u64 offset of the compat bit-matrix [N][n][bw]
@@ -76,7 +77,8 @@ struct LaunchPlan {
     int tmax;            // max threshold in the batch (template selector)
     int words;           // l-mer width (1 or 2)
     int search_blocks;   // persistent grid size
-    int compat_kernel;   // 1 VALU, 2 MFMA
+    int compat_kernel;   // 1 VALU
+    int split;           // third stack members one work item keeps
     int max_out_keys_lds;
 };
 

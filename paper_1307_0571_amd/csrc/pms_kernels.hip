@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
     const int inst = blockIdx.y;
     const InstDev I = insts[inst];
     const int u1 = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (u1 >= I.r) return;
+    if (u1 >= I.r || u1 < I.s1_lo || u1 >= I.s1_hi) return;
     const int lane = lane_id();
     const int n = I.n, bw = I.bw;
     if (n == 1) {
@@ -700,8 +700,8 @@ struct Searcher {
 };
 
 // Persistent search over one queue.  phase 0 takes the expansion's items;
-// when the string chosen at stack size 2 has more than kSplitTuples
-// survivors, the wave keeps ranks [0, kSplitTuples) and appends part items
+// when the string chosen at stack size 2 has more than `split` survivors,
+// the wave keeps ranks [0, split) and appends part items
 // for the rest to the part queue, which phase 0 never reads.  phase 1 (a
 // second launch after phase 0 has finished) takes the part items.  Every
 // wave leaves when its queue is empty; nothing waits on another wave.
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                                                Node* __restrict__ node_scratch,
                                                uint64_t* __restrict__ keys,
                                                InstCounters* __restrict__ ctr,
-                                               int level_words, int phase) {
+                                               int level_words, int phase, int split) {
     extern __shared__ uint64_t dyn[];
     __shared__ SearchLds<W, TMAX> S;
     __shared__ unsigned cntw[(TMAX + 1) * kMaxN];
@@ -774,20 +774,20 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                 if (k == 2) {
                     const int c = uni((int)sr.cnt16(2, p));
                     if (phase == 0) {
-                        if (c > kSplitTuples) {
-                            const int extra = (c - 1) / kSplitTuples;
+                        if (c > split) {
+                            const int extra = (c - 1) / split;
                             unsigned long long base = 0;
                             if (lane == 0) base = atomicAdd(&qp->item_count, (unsigned long long)extra);
                             base = __shfl(base, 0, 64);
                             if (base + (unsigned long long)extra <= qp->item_cap) {
                                 for (int e = lane; e < extra; e += 64)
-                                    parts[base + e] = item | ((uint64_t)((e + 1) * kSplitTuples) << 32);
-                                rank2_end = kSplitTuples;
+                                    parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
+                                rank2_end = split;
                             }
                         }
                     } else {
                         rank2 = lo;
-                        rank2_end = lo + kSplitTuples;
+                        rank2_end = lo + split;
                         cur = uni(sr.nth_bit(2, p, lo));
                         if (cur < 0) cur = 64 * I.bw;
                     }
@@ -1010,7 +1010,7 @@ static hipError_t search_t(const LaunchPlan& p, const DevBufs& b, hipStream_t st
     for (int phase = 0; phase < 2; phase++) {
         hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
                            (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.q, b.nodes, b.keys,
-                           b.ctr, p.level_words, phase);
+                           b.ctr, p.level_words, phase, p.split);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -82,7 +82,7 @@ extern "C" int pms_default_threshold(int n, int m, int l, int d) {
 namespace {
 
 struct HostInst {
-    int n, m, l, d, t, triple;
+    int n, m, l, d, t, triple, s1_lo, s1_hi;
     std::string alpha;  // sorted
 };
 
@@ -211,6 +211,8 @@ size_t plan_layout(pms_batch* bt) {
         d.bw = (d.r + 63) / 64;
         d.t = h.t;
         d.triple = h.triple;
+        d.s1_lo = h.s1_lo;
+        d.s1_hi = h.s1_hi;
         d.chars_off = chars_off;
         d.lmer_off = lmer_off;
         d.compat_off = compat_off;
@@ -234,6 +236,7 @@ size_t plan_layout(pms_batch* bt) {
     const int wpc = bt->tune.waves_per_cu > 0 ? bt->tune.waves_per_cu : 20;
     p.search_blocks = device_cus() * wpc;
     p.compat_kernel = 1;
+    p.split = bt->tune.split > 0 ? (int)bt->tune.split : kSplitDefault;
     const int64_t lmer_bytes = bt->words == 1 ? 8 : 16;
     size_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -371,6 +374,13 @@ int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
 int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pms_batch** out) {
     if (!out || count < 0 || (count > 0 && !inst)) return PMS_E_INVAL;
     if (count > kMaxInst) return PMS_E_UNSUPPORTED;
+    if (tune) {
+        if (tune->compat_kernel > 1) return PMS_E_UNSUPPORTED;
+        if (tune->split > 2047) return PMS_E_INVAL;
+        if (tune->s1_begin < 0 || tune->s1_end < 0 ||
+            (tune->s1_end > 0 && tune->s1_begin > tune->s1_end))
+            return PMS_E_INVAL;
+    }
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
     if (tune) bt->tune = *tune;
@@ -386,6 +396,10 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         h.t = bt->tune.threshold > 0 ? std::max(2, std::min(kMaxT, (int)bt->tune.threshold))
                                      : pms_default_threshold(h.n, h.m, h.l, h.d);
         h.triple = bt->tune.triple_filter < 0 ? 0 : 1;  // 0 = automatic = on
+        const int r = h.m >= h.l ? h.m - h.l + 1 : 0;
+        const bool all = bt->tune.s1_begin == 0 && bt->tune.s1_end == 0;
+        h.s1_hi = all ? r : std::min(r, (int)bt->tune.s1_end);
+        h.s1_lo = all ? 0 : std::min(h.s1_hi, (int)bt->tune.s1_begin);
         if (h.l > 32) wide = true;
     }
     if (bt->tune.lmer_words == 1 && wide) {

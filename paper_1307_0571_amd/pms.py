@@ -46,16 +46,18 @@ class _Result(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    """Search parameters (0 = automatic); none of them changes the result."""
+    """Search parameters (0 = automatic); none of them changes the result
+    except s1_begin / s1_end, which restrict the search to those S_1 windows."""
     _fields_ = [("threshold", ctypes.c_int32), ("lmer_words", ctypes.c_int32),
                 ("triple_filter", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("compat_kernel", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("s1_begin", ctypes.c_int32), ("s1_end", ctypes.c_int32),
                 ("out_capacity", ctypes.c_int64)]
 
     def __init__(self, threshold=0, lmer_words=0, triple_filter=0, waves_per_cu=0,
-                 compat_kernel=0, split=0, out_capacity=0):
+                 compat_kernel=0, split=0, s1_begin=0, s1_end=0, out_capacity=0):
         super().__init__(threshold, lmer_words, triple_filter, waves_per_cu, compat_kernel,
-                         split, out_capacity)
+                         split, s1_begin, s1_end, out_capacity)
 
 
 class Work(ctypes.Structure):

@@ -70,6 +70,7 @@ def test_plain_gpu_config_seed0(l, d):
 @pytest.mark.parametrize("tune", [
     dict(threshold=2), dict(threshold=3), dict(threshold=4), dict(threshold=6),
     dict(triple_filter=-1), dict(lmer_words=2), dict(waves_per_cu=1), dict(out_capacity=1),
+    dict(split=1), dict(split=3), dict(split=2047), dict(threshold=4, split=1),
 ])
 def test_output_invariant_under_tuning(tune):
     _say(f"tune {tune}")
@@ -169,3 +170,56 @@ def test_serving_admission_and_errors():
         assert got == oracle.solve_a(inst.seqs, 9, 2)
     finally:
         srv.close()
+
+
+# S_1 windows are independent sub-problems (Section 2.3): the device search
+# restricted to windows [a, b) must return exactly what the oracle finds from
+# the same windows.
+@pytest.mark.parametrize("seed,l,d,a,b", [
+    (0, 13, 4, 100, 140), (1, 15, 5, 0, 24), (2, 15, 5, 570, 586), (3, 11, 3, 7, 8),
+])
+def test_s1_windows_vs_oracle(seed, l, d, a, b):
+    _say(f"({l},{d}) seed={seed} S1 windows [{a},{b})")
+    inst = I.planted(seed, l, d)
+    want = oracle.solve_b(inst.seqs, l, d, t=3, windows=(a, b))
+    got = _gpu(inst, pms.Tune(s1_begin=a, s1_end=b))
+    assert got == want
+
+
+def test_s1_windows_partition_the_result():
+    inst = I.planted(4, 13, 4)
+    whole = set(_gpu(inst))
+    parts = set()
+    for a in range(0, 588, 150):
+        parts |= set(_gpu(inst, pms.Tune(s1_begin=a, s1_end=a + 150)))
+    assert parts == whole
+
+
+def _is_motif(seqs, mot, d):
+    import numpy as np
+    code = {c: i for i, c in enumerate("ACGT")}
+    M = np.array([code[c] for c in mot], dtype=np.int8)
+    l = len(mot)
+    for s in seqs:
+        a = np.array([code[c] for c in s], dtype=np.int8)
+        win = np.lib.stride_tricks.sliding_window_view(a, l)
+        if int((win != M).sum(axis=1).min()) > d:
+            return False
+    return True
+
+
+# Large instances with 128-bit l-mers: exact parity on a sample of S_1
+# windows (the oracle finishes those in seconds), every reported motif
+# checked by brute force, and the planted motif found from the window where
+# it was planted.
+def test_large_19_7_windows_vs_oracle():
+    inst = I.planted(0, 19, 7)
+    a, b = 40, 46
+    _say(f"(19,7) seed=0 S1 windows [{a},{b})")
+    want = oracle.solve_b(inst.seqs, 19, 7, t=3, windows=(a, b))
+    got = _gpu(inst, pms.Tune(s1_begin=a, s1_end=b, lmer_words=2))
+    assert got == want
+    st = inst.starts[0]
+    got_p = _gpu(inst, pms.Tune(s1_begin=st, s1_end=st + 1))
+    assert inst.motif in got_p
+    assert all(_is_motif(inst.seqs, x, 7) for x in got_p)

@@ -94,3 +94,22 @@ def test_workspace_size_is_host_only(lib):
     r = 200 - 9 + 1
     # at least the compat bit-matrix: N * n * ceil(r/64) words
     assert sz.value >= (10 * r) * 10 * ((r + 63) // 64) * 8
+
+
+def test_tune_validation_is_host_only(lib):
+    inst = I.planted(3, 9, 2, 10, 200)
+    mar = pms._Marshal([pms.Problem(inst.seqs, 9, 2)])
+    sz = ctypes.c_size_t(0)
+
+    def st(**kw):
+        t = pms.Tune(**kw)
+        return lib.pms_batch_workspace_size(mar.arr, 1, ctypes.byref(t), ctypes.byref(sz))
+
+    assert st() == pms.PMS_OK
+    assert st(s1_begin=5, s1_end=9) == pms.PMS_OK
+    assert st(s1_begin=0, s1_end=10_000) == pms.PMS_OK          # clamped to the last window
+    assert st(s1_begin=9, s1_end=5) == pms.PMS_E_INVAL
+    assert st(s1_begin=-1, s1_end=5) == pms.PMS_E_INVAL
+    assert st(split=2048) == pms.PMS_E_INVAL
+    assert st(split=1) == pms.PMS_OK
+    assert st(compat_kernel=2) == pms.PMS_E_UNSUPPORTED       # no MFMA builder in this version
