@@ -330,6 +330,18 @@ struct Searcher {
         return ballot(bad) == 0ull;
     }
 
+    // string index of flattened row word i (i < n * bw <= 1024): an exact
+    // reciprocal multiply instead of a division
+    __device__ __forceinline__ int row_of(int i) const {
+        return (int)(((unsigned)i * (unsigned)inv_bw) >> 16);
+    }
+
+    // Lanes over the row words of the remaining strings: child = parent AND
+    // compat(top).  With the Theorem 1 filter, the set bits of each block of
+    // 64 words are listed in LDS (the staging buffer, kVCap entries per
+    // pass: l-mer index and word/bit) by a wave prefix sum, lanes then test
+    // one listed survivor each (independent l-mer loads) and clear the
+    // failures with an LDS atomic AND.  Counts are taken afterwards.
     template <typename PP>
     __device__ __forceinline__ void filter_body(PP parent, const uint64_t* Cu, const Lm<W>& top,
                                                 int k, uint32_t rows) {
@@ -337,31 +349,71 @@ struct Searcher {
         uint64_t* child = level(k + 1);
         const int total = I.n * bw;
         const int thr3 = 3 * I.d;
+        Lm<W> sa[TMAX];
+        M ea[TMAX];
+        int ha[TMAX];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            const int aa = a < k ? a : 0;
+            sa[a] = S.st[aa];
+            ea[a] = S.E[aa][k];
+            ha[a] = S.HD[aa][k];
+        }
         for (int i0 = 0; i0 < total; i0 += 64) {
             const int i = i0 + lane;
-            const int j = i / bw;
-            if (i < total && ((rows >> j) & 1u)) {
-                const int w = i - j * bw;
-                uint64_t nb = parent[i] & Cu[i];
-                if (I.triple) {
-                    uint64_t bits = nb;
-                    while (bits) {
-                        const int b = __builtin_ctzll(bits);
-                        bits &= bits - 1;
-                        const Lm<W> v = L[j * r + w * 64 + b];
-                        const M dv = dmask(top, v);
-                        const int hv = pc(dv);
+            const int j = row_of(i);
+            const bool act = i < total && ((rows >> j) & 1u);
+            const uint64_t nb = act ? (parent[i] & Cu[i]) : 0ull;
+            if (act) child[i] = nb;
+            if (!I.triple) continue;
+            const int c = pc(nb);
+            const int incl = wave_incl_scan(c);
+            const int T = __shfl(incl, 63, 64);
+            const int w = i - j * bw;
+            for (int lo = 0; lo < T; lo += kVCap) {
+                // list the bits of rank [lo, lo + kVCap) of this block
+                int rank = incl - c;
+                uint64_t bits = nb;
+                while (bits && rank < lo + kVCap) {
+                    const int bb = __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    if (rank >= lo) {
+                        S.vset[rank - lo].h = (M)(j * r + w * 64 + bb);
+                        S.vset[rank - lo].lo = (M)((i << 6) | bb);
+                    }
+                    rank++;
+                }
+                __syncthreads();
+                const int cnt = T - lo < kVCap ? T - lo : kVCap;
+                for (int q0 = 0; q0 < cnt; q0 += 64) {
+                    const int q = q0 + lane;
+                    if (q < cnt) {
+                        const int g = (int)S.vset[q].h;
+                        const int e = (int)S.vset[q].lo;
+                        const Lm<W> v = L[g];
+                        const int hv = pc(dmask(top, v));
                         bool ok = true;
-                        for (int a = 0; a < k; a++) {
-                            const M da = dmask(S.st[a], v);
-                            const int cd = S.HD[a][k] + pc(da) + hv - pc((M)(S.E[a][k] | da));
-                            ok &= cd <= thr3;
+#pragma unroll
+                        for (int a = 0; a < TMAX; a++) {
+                            if (a < k) {
+                                const M da = dmask(sa[a], v);
+                                ok &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
+                            }
                         }
-                        if (!ok) nb &= ~(1ull << b);
+                        if (!ok)
+                            atomicAnd((unsigned long long*)&child[e >> 6], ~(1ull << (e & 63)));
                     }
                 }
-                child[i] = nb;
-                if (nb) atomicAdd(&cnt_word(k + 1, j), (unsigned)pc(nb));
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        for (int i0 = 0; i0 < total; i0 += 64) {
+            const int i = i0 + lane;
+            const int j = row_of(i);
+            if (i < total && ((rows >> j) & 1u)) {
+                const int c = pc(child[i]);
+                if (c) atomicAdd(&cnt_word(k + 1, j), (unsigned)c);
             }
         }
     }
@@ -370,6 +422,7 @@ struct Searcher {
     __device__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
     __device__ unsigned cnt16(int k, int j) { return cntw[k * kMaxN + j]; }
     unsigned* cntw;
+    int inv_bw;  // ceil(65536 / bw)
 
     __device__ int choose_row(int k) {
         const uint32_t rows = S.rows[k];
@@ -521,12 +574,14 @@ struct Searcher {
         if (mine) S.rowbase[lane] = S.voff[rank];
         const int natural = incl - c;  // start of this string in index order
         __syncthreads();
+        // slot -> l-mer index first (ALU only), then one independent load per
+        // slot
         const uint64_t* lvk = level(k);
         const int total = n * I.bw;
         int done = 0;
         for (int i0 = 0; i0 < total; i0 += 64) {
             const int i = i0 + lane;
-            const int j = i / I.bw;
+            const int j = row_of(i);
             uint64_t bits = (i < total && ((rows >> j) & 1u)) ? lvk[i] : 0ull;
             const int cb = pc(bits);
             const int inc = wave_incl_scan(cb);
@@ -536,10 +591,12 @@ struct Searcher {
             while (bits) {
                 const int b = __builtin_ctzll(bits);
                 bits &= bits - 1;
-                S.vset[o++] = L[j * I.r + w * 64 + b];
+                S.vset[o++].h = (M)(j * I.r + w * 64 + b);
             }
             done += __shfl(inc, 63, 64);
         }
+        __syncthreads();
+        for (int q = lane; q < tot; q += 64) S.vset[q] = L[(int)S.vset[q].h];
         __syncthreads();
         return true;
     }
@@ -744,6 +801,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
                              compat + I.compat_off, (uint64_t)u1, nodes, keys, ctr, lane};
         sr.cntw = cntw;
+        sr.inv_bw = (65536 + I.bw - 1) / (I.bw > 0 ? I.bw : 1);
         if (lane == 0) {
             S.st[0] = sr.L[u1];
             S.rows[1] = (I.n >= 32 ? 0xFFFFFFFFu : ((1u << I.n) - 1u)) & ~1u;
