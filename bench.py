@@ -46,13 +46,18 @@ def lane_ops(u: dict) -> float:
 
 
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_search_traffic_plain_13_4_15_5.json")
-KERNEL_SRC = os.path.join(HERE, "paper_1307_0571_amd", "csrc", "pms_kernels.hip")
+KERNEL_SRCS = [os.path.join(HERE, "paper_1307_0571_amd", "csrc", f)
+               for f in ("pms_kernels.hip", "pms_internal.h", "pms_runtime.cpp")]
 
 
 def kernel_sha256() -> str:
+    """SHA-256 over the kernel source and the launch parameters' sources."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def load_traffic():

@@ -92,7 +92,7 @@ typedef struct {
     int32_t split;          /* candidates for the third stack member one work
                                item keeps; the rest become part items of this
                                many each, searched by a second launch (1..2047;
-                               0 = 8) */
+                               0 = 16) */
     int32_t s1_begin;       /* search only the S_1 windows [s1_begin, s1_end) */
     int32_t s1_end;         /* (Section 2.3's independent sub-problems).  The
                                result is then the motifs that are within d of

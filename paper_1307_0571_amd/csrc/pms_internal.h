@@ -16,7 +16,7 @@ constexpr int kCandCap = 128;    // candidate buffer in LDS
 constexpr int kNodeBatch = 16;   // generator nodes expanded per wave step (x4 children)
 constexpr int kNodeCap = 4 * kNodeBatch * kMaxL;  // node stack bound per wave (see search)
 constexpr int kRing = 128;       // top of the node stack kept in LDS (power of two, >= 128)
-constexpr int kSplitDefault = 8;  // third stack members one work item keeps (rest: part items)
+constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
 constexpr int kMaxInst = 1 << 21;  // instances per batch (21-bit field of a work item)
 
 // Work item (64 bits): inst << 43 | lo << 32 | u1 << 16 | p2 << 11 | x2.
