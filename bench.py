@@ -216,7 +216,7 @@ def main():
                     help="serving: offered rate as a fraction of the batched capacity on the same mix")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
     from paper_1307_0571_amd import instances as I

@@ -12,7 +12,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
-    assert "one GPU" in msg["error"]
+    assert "one GPU only" in msg["error"]
 
 
 def test_lane_op_model_counts_every_unit():
