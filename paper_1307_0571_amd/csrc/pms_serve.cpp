@@ -1,17 +1,23 @@
 // Serving: continuous batching of independent requests (pms_stream_*).
 //
-// Requests are validated and copied on submit.  Worker threads repeatedly
-// form a device pass from the queued requests (oldest first), admitting a
-// request while the pass's planned device memory plus what other passes hold
-// stays within the stream's cap, and run the pass with the batched pipeline
+// Requests are validated and copied on submit, with an estimate of their
+// work: the Appendix D cost model at its best stack size plus the Appendix C
+// expected number of spurious motifs (the output the search must emit and
+// check).  Worker threads repeatedly form a device pass from the queue:
+// requests that have waited longer than kAgeLimit first (oldest first), then
+// the cheapest, admitting a request while the pass's planned device memory
+// plus what other passes hold stays within the stream's cap, and without
+// mixing requests whose estimates differ by more than kMixRatio (a pass lasts
+// as long as its heaviest member).  The pass runs with the batched pipeline
 // (one launch per phase for all its instances).  A request that arrives while
-// a pass is on the device joins the next pass a worker forms; with more than
-// one worker, passes overlap on the device.  Each ticket's result is the set
-// the instance has alone: instances in a pass never share data.
+// a pass is on the device joins a later pass; with more than one worker,
+// passes overlap on the device.  Each ticket's result is the set the instance
+// has alone: instances in a pass never share data.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -36,7 +42,41 @@ struct Request {
     int status = PMS_E_AGAIN;
     pms_result result{};
     bool taken = false;   // result handed to the caller
+    double est = 0;       // estimated work (arbitrary units, for ordering)
+    std::chrono::steady_clock::time_point t_submit;
 };
+
+constexpr double kAgeLimitS = 30.0;  // waited longer: admitted first, oldest first
+constexpr double kMixRatio = 16.0;   // largest / smallest estimate within one pass
+
+// |{x : Hd(x, u) <= d}| for one l-mer u over a 4-letter alphabet (Appendix C).
+double ball(int l, int d) {
+    double s = 0, c = 1;  // c = C(l, i)
+    for (int i = 0; i <= d && i <= l; i++) {
+        s += c * std::pow(3.0, i);
+        c = c * (l - i) / (i + 1);
+    }
+    return s;
+}
+
+// Appendix D cost model at its best stack size plus the Appendix C expected
+// number of l-mers within d of some window of every string, weighted by l.
+double estimate(int n, int m, int l, int d) {
+    const int r = m - l + 1;
+    if (r <= 0) return 0;
+    const double nd = ball(l, d), n2d = ball(l, 2 * d), all = std::pow(4.0, l);
+    const double p = std::min(1.0, n2d / all), q = nd / n2d;
+    double best = INFINITY, ts = 0;
+    for (int t = 1; t <= n; t++) {
+        const double lt = t * std::log((double)r) + 0.5 * t * (t - 1) * std::log(p);
+        ts += (double)n * l * std::exp(std::min(lt, 700.0));
+        const double tp = std::exp(std::min(lt + std::log(nd) + (t - 1) * std::log(q), 700.0)) * l;
+        best = std::min(best, ts + tp);
+    }
+    const double hit = 1.0 - std::pow(1.0 - std::min(1.0, nd / all), (double)r);
+    const double spurious = all * std::pow(hit, (double)n);
+    return best + spurious * l * n * r;
+}
 
 }  // namespace
 
@@ -73,26 +113,45 @@ void worker(pms_stream* s) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
             if (s->queue.empty()) return;  // stopping and nothing queued
-            // admit oldest-first while the pass fits the memory cap
+            // order: aged requests (oldest first), then the cheapest
+            const auto now = std::chrono::steady_clock::now();
+            std::vector<std::shared_ptr<Request>> order(s->queue.begin(), s->queue.end());
+            auto aged = [&](const std::shared_ptr<Request>& r) {
+                return std::chrono::duration<double>(now - r->t_submit).count() > kAgeLimitS;
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](const std::shared_ptr<Request>& a, const std::shared_ptr<Request>& b) {
+                                 const bool xa = aged(a), xb = aged(b);
+                                 if (xa != xb) return xa;
+                                 if (xa) return a->ticket < b->ticket;
+                                 return a->est < b->est;
+                             });
+            // admit in that order while the pass fits the memory cap
             const size_t cap = (size_t)s->cfg.device_mem_cap;
-            while (!s->queue.empty() && (int)pass.size() < s->cfg.max_wave &&
-                   s->inflight + (int)pass.size() < s->cfg.max_inflight) {
-                auto r = s->queue.front();
+            double lo_est = 0;
+            for (auto& r : order) {
+                if ((int)pass.size() >= s->cfg.max_wave ||
+                    s->inflight + (int)pass.size() >= s->cfg.max_inflight)
+                    break;
+                if (!pass.empty() && !aged(r) && r->est > kMixRatio * std::max(lo_est, 1.0)) continue;
                 pass.push_back(r);
                 size_t b = pass_bytes(pass, tune);
                 if (b == SIZE_MAX || s->held + b > cap) {
                     pass.pop_back();
-                    break;
+                    if (pass.empty()) break;  // the first choice does not fit now
+                    continue;
                 }
                 bytes = b;
-                s->queue.pop_front();
+                if (pass.size() == 1) lo_est = r->est;
             }
+            for (auto& r : pass) s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
             if (pass.empty()) {
-                // the oldest request does not fit next to what is running:
-                // wait for a pass to finish (or fail it if nothing runs)
+                // the first request in admission order does not fit next to
+                // what is running: wait for a pass to finish (or fail it if
+                // nothing runs)
                 if (s->held == 0) {
-                    auto r = s->queue.front();
-                    s->queue.pop_front();
+                    auto r = order.front();
+                    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
                     r->status = PMS_E_NOMEM;
                     s->cv_done.notify_all();
                 } else {
@@ -178,6 +237,8 @@ int pms_stream_submit(pms_stream* s, const pms_instance* inst, uint64_t* ticket)
     if (rc) return rc;
     if (b > (size_t)s->cfg.device_mem_cap) return PMS_E_NOMEM;
     r->bytes = b;
+    r->est = estimate(r->inst.n, r->inst.m, r->inst.l, r->inst.d);
+    r->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return PMS_E_ABORTED;
     r->ticket = s->next_ticket++;

@@ -172,6 +172,23 @@ def test_serving_admission_and_errors():
         srv.close()
 
 
+def test_serving_memory_cap_and_mixed_costs():
+    _say("serving: a memory cap that admits about one instance per pass, mixed (l,d)")
+    insts = I.batch_mix(2100, 8, ld=((9, 2), (11, 3), (13, 4)), n_range=(6, 10),
+                        m_range=(150, 250))
+    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+    one = max(pms.Batch.workspace_size([p]) for p in probs)
+    srv = pms.Server(device_mem_cap=int(one * 1.2))
+    try:
+        tickets = [srv.submit(p) for p in probs]
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for x, g in zip(insts, got):
+        assert g == _gpu(x)
+        assert x.motif in g
+
+
 # S_1 windows are independent sub-problems (Section 2.3): the device search
 # restricted to windows [a, b) must return exactly what the oracle finds from
 # the same windows.
