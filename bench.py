@@ -174,23 +174,52 @@ def run_serving(args, I, pms):
     rate = max(1e-3, args.load * capacity)
     rng = random.Random(7)
     srv = pms.Server()
-    sent = {}
+    import threading
+    lock = threading.Lock()
+    pending = {}   # ticket -> (submit time, instance)
+    done = []      # (latency, instance, result)
+    submitting = [True]
+
+    def collect():
+        # completion times: poll every outstanding ticket every millisecond,
+        # independently of the submitting loop
+        while True:
+            with lock:
+                tickets = list(pending.items())
+                more = submitting[0]
+            if not tickets and not more:
+                return
+            for tk, (ts, x) in tickets:
+                r = srv.poll(tk)
+                if r is not None:
+                    done.append((time.perf_counter() - ts, x, r))
+                    with lock:
+                        del pending[tk]
+            time.sleep(0.001)
+
+    th = threading.Thread(target=collect)
     t0 = time.perf_counter()
+    th.start()
     next_t = 0.0
     for i, x in enumerate(insts):
         next_t += rng.expovariate(rate)
         now = time.perf_counter() - t0
         if next_t > now:
             time.sleep(next_t - now)
-        sent[srv.submit(pms.Problem(x.seqs, x.l, x.d))] = (time.perf_counter(), x)
-    lat = []
-    for tk, (ts, x) in sent.items():
-        r = srv.wait(tk)
-        lat.append(time.perf_counter() - ts)
-        if x.motif not in r:
-            raise SystemExit(f"planted motif missing in served request seed {x.seed}")
+        ts = time.perf_counter()
+        tk = srv.submit(pms.Problem(x.seqs, x.l, x.d))
+        with lock:
+            pending[tk] = (ts, x)
+    with lock:
+        submitting[0] = False
+    th.join()
     total = time.perf_counter() - t0
     srv.close()
+    lat = []
+    for (lt, x, r) in done:
+        lat.append(lt)
+        if x.motif not in r:
+            raise SystemExit(f"planted motif missing in served request seed {x.seed}")
     lat.sort()
     return {"requests": len(insts), "capacity_instances_per_s": capacity, "offered_rate": rate,
             "instances_per_s": len(insts) / total,
