@@ -3,7 +3,10 @@
 // reports for k_copy, divided by the bytes it must read / write, gives the
 // factor by which the same counters over- or under-count for any kernel.
 //
-// Usage: hbm_copy [MiB]   (default 256; copies that many MiB three times)
+// Measurement tooling for the benchmark's traffic figures, not part of the
+// library.  Build and run (on the GPU host):
+//   hipcc --offload-arch=gfx950 -O3 -o _build/hbm_copy hbm_copy.hip
+//   _build/hbm_copy [MiB]   (default 256; copies that many MiB three times)
 #include <hip/hip_runtime.h>
 
 #include <cstdio>

@@ -77,7 +77,7 @@ typedef struct {
 /* Search parameters.  Zero / negative fields mean "choose automatically".
  * None of them except s1_begin / s1_end changes the result set (the method
  * is exact for every setting); they change only speed and memory. */
-typedef struct {
+typedef struct pms_tune {
     int32_t threshold;      /* stack size t at which the search switches to
                                neighbourhood generation (Section 2.2,
                                Appendix D); 2..8, 0 = cost model */
@@ -99,7 +99,9 @@ typedef struct {
                                one of those windows.  0, 0 = every window;
                                end beyond the last window is clamped;
                                begin > end (end > 0) is PMS_E_INVAL */
-    int64_t out_capacity;   /* initial motif slots per instance (pre-dedup); 0 = auto */
+    int64_t out_capacity;   /* motif slots per instance (before removal of
+                               repeats); 0 = sized from the Appendix C expected
+                               number of motifs (pms_expected_motifs) */
 } pms_tune;
 
 /* Solve one instance (Section 1 problem statement).  Blocks until done. */
@@ -109,8 +111,9 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabe
 /* Solve `count` instances of any mix of (l, d, n, m) in one device pass: one
  * pack launch, one compat launch, a persistent search fed by a device work
  * queue (two launches: the level-2 work items, then the parts of items too
- * large for one wave), one sort/unique launch.  outs[i] receives instance
- * i's set.  tune may be NULL.  At most 2^21 instances per call
+ * large for one wave), one sort/unique launch, all enqueued back to back on
+ * hip_stream (NULL = a stream of the library's own).  outs[i] receives
+ * instance i's set.  tune may be NULL.  At most 2^21 instances per call
  * (PMS_E_UNSUPPORTED beyond). */
 int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
                     const pms_tune* tune, void* hip_stream);
@@ -120,20 +123,27 @@ typedef struct pms_batch pms_batch;
 
 /* Validate, encode and upload the instances; plan and allocate device memory.
  * If workspace is non-NULL it must be device memory of at least
- * pms_batch_workspace_size() bytes, borrowed for the batch's lifetime;
- * otherwise the library allocates. */
+ * pms_batch_workspace_size() bytes, borrowed for the batch's lifetime
+ * (PMS_E_NOMEM if smaller); otherwise the library allocates.  The uploads
+ * are enqueued on a stream of the batch's own; every later run waits for
+ * them on its own stream. */
 int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tune,
                      void* workspace, size_t workspace_bytes, pms_batch** out);
 /* Device bytes a batch of these instances needs (for a caller workspace). */
 int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_tune* tune,
                              size_t* bytes);
-/* Run the whole device pipeline on hip_stream (inputs already in HBM).  Each
- * phase is synchronised before the next is launched.  use_graph != 0
- * (hipGraph replay of the same launches) is not available in this version
- * and returns PMS_E_UNSUPPORTED. */
+/* Enqueue the whole device pipeline on hip_stream (NULL = the batch's own
+ * stream; inputs already in HBM) and return without waiting.  The phases
+ * are launched back to back; stream order sequences them.  use_graph != 0
+ * captures the same launches into a hipGraph on the first call (per
+ * stream) and replays it on later calls; no memset node is recorded (the
+ * counters are cleared by a kernel).  A launch error makes the batch
+ * unusable: later calls return the same status. */
 int pms_batch_run(pms_batch* b, void* hip_stream, int32_t use_graph);
-/* Wait for the last run, copy the sets back.  outs has one slot per
- * instance.  Re-runs internally (larger output buffers) if a run overflowed. */
+/* Wait for the last run (its stream only), copy the sets back.  outs has
+ * one slot per instance.  An instance whose motifs outnumbered its output
+ * slots is solved again alone, in library-allocated device memory with
+ * slots for all of them; the other results come from the run itself. */
 int pms_batch_results(pms_batch* b, pms_result* outs);
 /* Per-phase device times of the last run in milliseconds (pack, compat,
  * expand, search, sort), measured with HIP events on the run's stream. */
@@ -161,12 +171,19 @@ typedef struct {
 } pms_work;
 int pms_batch_work(pms_batch* b, int32_t instance, pms_work* out);
 
-/* ---- serving: continuous batching with admission by device memory ---- */
+/* ---- serving: continuous batching with admission by device memory ----
+ * The stream owns one device pool of device_mem_cap bytes (allocated on the
+ * first pass).  `workers` threads each form a device pass from the queued
+ * requests whenever they are free and run it on their own non-blocking
+ * stream in a block of the pool, so passes overlap on the device; a request
+ * is admitted when its memory bound fits in the pool beside the passes
+ * already running. */
 typedef struct {
-    int64_t device_mem_cap;  /* bytes the stream may hold on the device; 0 = 64 GiB */
+    int64_t device_mem_cap;  /* device pool bytes; 0 = 32 GiB */
     int32_t max_inflight;    /* instances resident at once; 0 = 256 */
     int32_t max_wave;        /* instances admitted per device pass; 0 = 64 */
     pms_tune tune;
+    int32_t workers;         /* passes on the device at once; 0 = 3 (at most 16) */
 } pms_stream_config;
 
 typedef struct pms_stream pms_stream;
@@ -181,6 +198,14 @@ int pms_stream_poll(pms_stream* s, uint64_t ticket, pms_result* out);
 int pms_stream_wait(pms_stream* s, uint64_t ticket, pms_result* out, int64_t timeout_us);
 /* Finishes in-flight work, fails queued tickets with PMS_E_ABORTED, frees. */
 int pms_stream_destroy(pms_stream* s);
+
+/* Appendix D cost-model threshold the library uses when tune.threshold is 0
+ * (a stack size in [2, 8]); host-only. */
+int pms_default_threshold(int n, int m, int l, int d);
+/* Appendix C expected number of motifs of a random DNA instance (n strings
+ * of length m, i.i.d. uniform bases): 4^l (1 - (1 - N_d / 4^l)^(m-l+1))^n;
+ * host-only.  Sizes the output slots when tune.out_capacity is 0. */
+double pms_expected_motifs(int n, int m, int l, int d);
 
 /* Number of visible GPUs (0 when none; never an error for "no device"). */
 int pms_device_count(int32_t* count);

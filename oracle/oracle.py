@@ -32,6 +32,10 @@ class _Stats(ctypes.Structure):
         ("motifs", ctypes.c_int64),
         ("filter_tests", ctypes.c_int64),
         ("verify_tests", ctypes.c_int64),
+        ("push_tries", ctypes.c_int64),
+        ("filter_words", ctypes.c_int64),
+        ("compat_pass", ctypes.c_int64),
+        ("triple_tests", ctypes.c_int64),
     ]
 
 
@@ -186,7 +190,9 @@ def solve_b(seqs: Sequence[str] = None, l: int = 0, d: int = 0, alphabet: str = 
             "pushes": [int(x) for x in st.pushes],
             "tuples": st.tuples, "gen_nodes": st.gen_nodes, "leaves": st.leaves,
             "motifs": st.motifs, "filter_tests": st.filter_tests,
-            "verify_tests": st.verify_tests, "t": t,
+            "verify_tests": st.verify_tests, "push_tries": st.push_tries,
+            "filter_words": st.filter_words, "compat_pass": st.compat_pass,
+            "triple_tests": st.triple_tests, "t": t,
         }
         return res, info
     return res

@@ -1,5 +1,4 @@
-"""Build libpms.so (gfx950) in-tree with hipcc, and the hbm_copy
-calibration program used to scale HBM traffic counters."""
+"""Build libpms.so (gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
 import os
@@ -8,7 +7,6 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpms.so")
-COPY = os.path.join(HERE, "hbm_copy")
 SOURCES = ["pms_kernels.hip", "pms_runtime.cpp", "pms_serve.cpp"]
 ARCH = os.environ.get("PMS_OFFLOAD_ARCH", "gfx950")
 
@@ -24,14 +22,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
-    copy_cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17",
-                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-Wno-unused-command-line-argument",
-                "-o", COPY + ".tmp", os.path.join(CSRC, "hbm_copy.hip")]
-    if verbose:
-        print(" ".join(copy_cmd))
-    subprocess.run(copy_cmd, check=True)
-    os.replace(COPY + ".tmp", COPY)
     return LIB
 
 

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+struct pms_tune;  // include/pms.h
+
 namespace pms {
 
 // Limits of the device path.
@@ -106,5 +108,10 @@ hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
 hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 size_t search_lds_bytes(const LaunchPlan& p);
+
+// Memory plan bounds (pms_runtime.cpp): a batch needs at most
+// fixed_bytes(tune) + the sum of inst_bytes(...) over its instances.
+size_t inst_bytes(int n, int m, int l, int d, const ::pms_tune* tune);
+size_t fixed_bytes(const ::pms_tune* tune);
 
 }  // namespace pms

@@ -1,5 +1,12 @@
 // Host runtime of libpms: validation, memory planning, launches, results.
 // The C ABI is declared in include/pms.h.
+//
+// Streams: every stream the library creates is non-blocking, and every copy
+// is asynchronous on the batch's own stream followed by a wait on that
+// stream only, so batches on different streams (serving workers) overlap on
+// the device and never wait for each other.  The phases of one run are
+// launched back to back on the run's stream; stream order alone sequences
+// them (each phase reads only what earlier phases wrote).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,7 +86,30 @@ extern "C" int pms_default_threshold(int n, int m, int l, int d) {
     return std::max(2, std::min(kMaxT, t));
 }
 
+// Appendix C: the expected number of l-mers within d of some window of each
+// of n random strings, 4^l (1 - (1 - N_d / 4^l)^(m-l+1))^n.  Used to pre-size
+// an instance's output buffer (the planted motif plus the spurious ones).
+extern "C" double pms_expected_motifs(int n, int m, int l, int d) {
+    const int r = m - l + 1;
+    if (r <= 0 || n < 1 || l < 1 || d < 0) return 0.0;
+    const double all = std::pow(4.0, l);
+    const double p = std::min(1.0, ball_size(l, d) / all);
+    // 1 - (1 - p)^r without cancellation for tiny p
+    const double hit = -std::expm1((double)r * std::log1p(-std::min(p, 1.0 - 1e-300)));
+    return all * std::pow(hit, (double)n);
+}
+
 namespace {
+
+constexpr int64_t kOutCapMin = 256;
+constexpr int64_t kOutCapMax = int64_t(1) << 22;  // pre-sized slots; larger sets re-run alone
+
+int64_t presized_out_cap(int n, int m, int l, int d) {
+    const double e = pms_expected_motifs(n, m, l, d);
+    const double want = 2.0 * e + 64.0;
+    const int64_t c = want >= (double)kOutCapMax ? kOutCapMax : (int64_t)want;
+    return next_pow2(std::max(kOutCapMin, c));
+}
 
 struct HostInst {
     int n, m, l, d, t, triple, s1_lo, s1_hi;
@@ -122,6 +152,8 @@ int validate(const pms_instance& in, HostInst& h, std::vector<uint8_t>& chars,
     return PMS_OK;
 }
 
+// One cached arena for pms_solve / pms_solve_batch (one call at a time holds
+// it; a concurrent call allocates its own).
 struct DevCache {
     std::mutex mu;
     void* ptr = nullptr;
@@ -153,6 +185,8 @@ void cache_give(void* p) {
     if (p == g_cache.ptr) g_cache.busy = false;
 }
 
+hipError_t make_stream(hipStream_t* s) { return hipStreamCreateWithFlags(s, hipStreamNonBlocking); }
+
 }  // namespace
 
 struct pms_batch {
@@ -171,13 +205,15 @@ struct pms_batch {
     unsigned long long item_cap = 0;
     unsigned long long part_cap = 0;
     pms_tune tune{};
-    hipStream_t own_stream = nullptr;
-    hipStream_t last = nullptr;
-    hipGraph_t graph = nullptr;
+    hipStream_t own_stream = nullptr;  // uploads, and runs given no stream
+    hipEvent_t uploaded = nullptr;     // recorded on own_stream after the uploads
+    hipStream_t last = nullptr;        // stream of the last run
     hipGraphExec_t gexec = nullptr;
-    hipStream_t graph_stream = nullptr;
+    hipStream_t graph_stream = nullptr;  // stream the graph was captured on
     hipEvent_t ev[6] = {};
     bool timed = false;
+    bool ran = false;
+    int failed = PMS_OK;  // sticky error: the batch's device state is unusable
     int words = 1;
     std::vector<InstCounters> last_ctr;  // counters read back by the last results call
 };
@@ -270,6 +306,34 @@ size_t plan_layout(pms_batch* bt) {
     return off;
 }
 
+}  // namespace
+
+namespace pms {
+
+// Upper bound of the device bytes an instance adds to a batch (16-byte
+// l-mers and 2-word keys, whatever the batch's width).
+size_t inst_bytes(int n, int m, int l, int d, const pms_tune* tune) {
+    const int64_t r = m >= l ? m - l + 1 : 0;
+    const int64_t N = (int64_t)n * r, bw = (r + 63) / 64;
+    const int64_t cap = (tune && tune->out_capacity > 0) ? next_pow2(tune->out_capacity)
+                                                          : presized_out_cap(n, m, l, d);
+    return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 + N * 16 + N * n * bw * 8 +
+                    r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters));
+}
+
+// Device bytes of a batch that do not depend on its instances (part queue
+// bound, per-wave node areas, queue counters, region alignment).
+size_t fixed_bytes(const pms_tune* tune) {
+    const int wpc = (tune && tune->waves_per_cu > 0) ? tune->waves_per_cu : 20;
+    const int64_t blocks = (int64_t)device_cus() * wpc;
+    return (size_t)(((int64_t)1 << 22) * 8 + blocks * kNodeCap * (int64_t)sizeof(Node) +
+                    2 * (int64_t)sizeof(QueueCounters) + 16 * 256);
+}
+
+}  // namespace pms
+
+namespace {
+
 void resolve(pms_batch* bt) {
     char* a = (char*)bt->arena;
     bt->b.inst = (InstDev*)(a + (size_t)bt->b.inst);
@@ -287,9 +351,7 @@ void resolve(pms_batch* bt) {
 
 void release_arena(pms_batch* bt) {
     if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
-    if (bt->graph) (void)hipGraphDestroy(bt->graph);
     bt->gexec = nullptr;
-    bt->graph = nullptr;
     if (bt->arena) {
         if (bt->cached_arena) cache_give(bt->arena);
         else if (bt->own_arena) (void)hipFree(bt->arena);
@@ -298,7 +360,8 @@ void release_arena(pms_batch* bt) {
     bt->own_arena = bt->cached_arena = false;
 }
 
-// Allocate (or adopt the workspace), upload inputs.
+// Allocate (or adopt the workspace), then upload the inputs on the batch's
+// own stream; `uploaded` marks their completion for whichever stream runs.
 int materialise(pms_batch* bt, bool use_cache) {
     const size_t need = plan_layout(bt);
     bt->arena_bytes = need;
@@ -317,55 +380,42 @@ int materialise(pms_batch* bt, bool use_cache) {
         bt->arena = p;
     }
     resolve(bt);
-    hipError_t e;
-    e = hipMemcpy(bt->b.inst, bt->dinst.data(), bt->dinst.size() * sizeof(InstDev),
-                  hipMemcpyHostToDevice);
-    if (e == hipSuccess && !bt->chars.empty())
-        e = hipMemcpy(bt->b.chars, bt->chars.data(), bt->chars.size(), hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (!bt->own_stream) e = make_stream(&bt->own_stream);
+    if (e == hipSuccess && !bt->uploaded) e = hipEventCreateWithFlags(&bt->uploaded, hipEventDisableTiming);
+    hipStream_t s = bt->own_stream;
     if (e == hipSuccess)
-        e = hipMemcpy(bt->b.lut, bt->lut.data(), bt->lut.size(), hipMemcpyHostToDevice);
-    // A copy from pageable host memory may return once the data is staged,
-    // before it lands in HBM; the kernels run on another stream, so wait for
-    // the uploads here before anything can read them.
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+        e = hipMemcpyAsync(bt->b.inst, bt->dinst.data(), bt->dinst.size() * sizeof(InstDev),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !bt->chars.empty())
+        e = hipMemcpyAsync(bt->b.chars, bt->chars.data(), bt->chars.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->b.lut, bt->lut.data(), bt->lut.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(bt->uploaded, s);
     return hip_status(e);
 }
 
-// Every phase of the device pipeline is followed by a host synchronisation of
-// its stream.  Back-to-back launches without it (and hipGraph replay, which
-// launches the same way) failed on the GPU (a memory fault once, stalls
-// three times) while the phase-synchronous order ran correctly; the
-// asynchronous order stays off until that failure is understood.
+// The whole device pipeline on stream s, launched back to back.  With
+// `timed`, events between the phases give per-phase device times.
 int enqueue(pms_batch* bt, hipStream_t s, bool timed) {
-    static const char* kPhase[6] = {"reset", "pack", "compat", "expand", "search", "sort"};
-    (void)timed;
     hipError_t e = hipSuccess;
-    int phase = 0;
     auto rec = [&](int i) {
-        if (e == hipSuccess) e = hipEventRecord(bt->ev[i], s);
-    };
-    auto done = [&]() {
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return false;
-        phase++;
-        return true;
+        if (timed && e == hipSuccess) e = hipEventRecord(bt->ev[i], s);
     };
     rec(0);
-    bool ok = true;
-    if (ok) { e = launch_reset(bt->plan, bt->b, bt->item_cap, bt->part_cap, s); ok = done(); }
-    if (ok) { e = launch_pack(bt->plan, bt->b, s); ok = done(); }
+    if (e == hipSuccess) e = launch_reset(bt->plan, bt->b, bt->item_cap, bt->part_cap, s);
+    if (e == hipSuccess) e = launch_pack(bt->plan, bt->b, s);
     rec(1);
-    if (ok) { e = launch_compat(bt->plan, bt->b, s); ok = done(); }
+    if (e == hipSuccess) e = launch_compat(bt->plan, bt->b, s);
     rec(2);
-    if (ok) { e = launch_expand(bt->plan, bt->b, s); ok = done(); }
+    if (e == hipSuccess) e = launch_expand(bt->plan, bt->b, s);
     rec(3);
-    if (ok) { e = launch_search(bt->plan, bt->b, s); ok = done(); }
+    if (e == hipSuccess) e = launch_search(bt->plan, bt->b, s);
     rec(4);
-    if (ok) { e = launch_sort(bt->plan, bt->b, s); ok = done(); }
+    if (e == hipSuccess) e = launch_sort(bt->plan, bt->b, s);
     rec(5);
     if (e != hipSuccess) {
-        fprintf(stderr, "pms: phase %s failed: %s\n", kPhase[phase < 6 ? phase : 5],
-                hipGetErrorString(e));
+        fprintf(stderr, "pms: launch failed: %s\n", hipGetErrorString(e));
         return PMS_E_DEVICE;
     }
     return PMS_OK;
@@ -380,11 +430,13 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         if (tune->s1_begin < 0 || tune->s1_end < 0 ||
             (tune->s1_end > 0 && tune->s1_begin > tune->s1_end))
             return PMS_E_INVAL;
+        if (tune->out_capacity < 0) return PMS_E_INVAL;
     }
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
     if (tune) bt->tune = *tune;
     bt->hin.resize(count);
+    bt->out_cap.assign(count, kOutCapMin);
     bool wide = bt->tune.lmer_words == 2;
     for (int i = 0; i < count; i++) {
         int rc = validate(inst[i], bt->hin[i], bt->chars, bt->lut);
@@ -401,14 +453,14 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         h.s1_hi = all ? r : std::min(r, (int)bt->tune.s1_end);
         h.s1_lo = all ? 0 : std::min(h.s1_hi, (int)bt->tune.s1_begin);
         if (h.l > 32) wide = true;
+        bt->out_cap[i] = bt->tune.out_capacity > 0 ? next_pow2(bt->tune.out_capacity)
+                                                   : presized_out_cap(h.n, h.m, h.l, h.d);
     }
     if (bt->tune.lmer_words == 1 && wide) {
         delete bt;
         return PMS_E_UNSUPPORTED;
     }
     bt->words = wide ? 2 : 1;
-    const int64_t cap0 = bt->tune.out_capacity > 0 ? bt->tune.out_capacity : (1 << 14);
-    bt->out_cap.assign(count, next_pow2(cap0));
     *out = bt;
     return PMS_OK;
 }
@@ -433,11 +485,75 @@ void fill_result(const HostInst& h, const uint64_t* keys, int64_t cnt, int kw, p
     }
 }
 
+int batch_create_impl(const pms_instance* inst, int32_t count, const pms_tune* tune, void* ws,
+                      size_t ws_bytes, bool use_cache, const std::vector<int64_t>* caps,
+                      pms_batch** out);
+
+// Instances whose output overflowed their slots are solved again in a batch
+// of their own, with slots for every motif they emitted; the others keep
+// the first run's result.
+int rerun_overflowed(pms_batch* bt, const std::vector<int>& idx,
+                     const std::vector<InstCounters>& ctr, hipStream_t s, pms_result* outs) {
+    std::vector<std::vector<std::string>> strs(idx.size());
+    std::vector<std::vector<const char*>> ptrs(idx.size());
+    std::vector<std::string> alphas(idx.size());
+    std::vector<pms_instance> sub(idx.size());
+    std::vector<int64_t> caps(idx.size());
+    for (size_t k = 0; k < idx.size(); k++) {
+        const int i = idx[k];
+        const HostInst& h = bt->hin[i];
+        const InstDev& d = bt->dinst[i];
+        strs[k].resize(h.n);
+        ptrs[k].resize(h.n);
+        for (int j = 0; j < h.n; j++) {
+            strs[k][j].assign((const char*)&bt->chars[(size_t)d.chars_off + (size_t)j * h.m],
+                              (size_t)h.m);
+            ptrs[k][j] = strs[k][j].c_str();
+        }
+        alphas[k] = h.alpha;
+        sub[k] = pms_instance{ptrs[k].data(), h.n, h.m, alphas[k].c_str(), h.l, h.d};
+        caps[k] = next_pow2(std::max<int64_t>((int64_t)ctr[i].out_count, 1));
+    }
+    pms_tune t = bt->tune;  // same threshold, width and S_1 window range
+    pms_batch* sb = nullptr;
+    int rc = batch_create_impl(sub.data(), (int32_t)sub.size(), &t, nullptr, 0, false, &caps, &sb);
+    if (rc) return rc;
+    rc = pms_batch_run(sb, s, 0);
+    std::vector<pms_result> r(idx.size());
+    if (!rc) rc = pms_batch_results(sb, r.data());
+    pms_batch_destroy(sb);
+    if (rc) return rc;
+    for (size_t k = 0; k < idx.size(); k++) outs[idx[k]] = r[k];
+    return PMS_OK;
+}
+
+int batch_create_impl(const pms_instance* inst, int32_t count, const pms_tune* tune, void* ws,
+                      size_t ws_bytes, bool use_cache, const std::vector<int64_t>* caps,
+                      pms_batch** out) {
+    pms_batch* bt = nullptr;
+    int rc = make_batch(inst, count, tune, &bt);
+    if (rc) return rc;
+    if (caps)
+        for (int i = 0; i < count; i++) bt->out_cap[i] = (*caps)[i];
+    bt->ext_ws = ws;
+    bt->ext_ws_bytes = ws_bytes;
+    rc = materialise(bt, use_cache);
+    if (rc == PMS_OK) {
+        for (int i = 0; i < 6 && rc == PMS_OK; i++) rc = hip_status(hipEventCreate(&bt->ev[i]));
+    }
+    if (rc) {
+        pms_batch_destroy(bt);
+        return rc;
+    }
+    *out = bt;
+    return PMS_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* pms_version(void) { return "pms-mi355x 0.1 (gfx950)"; }
+const char* pms_version(void) { return "pms-mi355x 0.2 (gfx950)"; }
 
 int pms_device_count(int32_t* count) {
     if (!count) return PMS_E_INVAL;
@@ -484,41 +600,51 @@ int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_
     return PMS_OK;
 }
 
-static int batch_create_impl(const pms_instance* inst, int32_t count, const pms_tune* tune,
-                             void* ws, size_t ws_bytes, bool use_cache, pms_batch** out) {
-    pms_batch* bt = nullptr;
-    int rc = make_batch(inst, count, tune, &bt);
-    if (rc) return rc;
-    bt->ext_ws = ws;
-    bt->ext_ws_bytes = ws_bytes;
-    rc = materialise(bt, use_cache);
-    if (rc == PMS_OK) {
-        for (int i = 0; i < 6 && rc == PMS_OK; i++) rc = hip_status(hipEventCreate(&bt->ev[i]));
-    }
-    if (rc) {
-        pms_batch_destroy(bt);
-        return rc;
-    }
-    *out = bt;
-    return PMS_OK;
-}
-
 int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tune,
                      void* workspace, size_t workspace_bytes, pms_batch** out) {
-    return batch_create_impl(inst, count, tune, workspace, workspace_bytes, false, out);
+    return batch_create_impl(inst, count, tune, workspace, workspace_bytes, false, nullptr, out);
 }
 
 int pms_batch_run(pms_batch* bt, void* hip_stream, int32_t use_graph) {
     if (!bt) return PMS_E_INVAL;
+    if (bt->failed) return bt->failed;
+    if (!bt->arena) return PMS_E_INVAL;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (!s) {
-        if (!bt->own_stream && hipStreamCreate(&bt->own_stream) != hipSuccess) return PMS_E_DEVICE;
-        s = bt->own_stream;
-    }
+    if (!s) s = bt->own_stream;
+    // the uploads (own stream) precede every run, whichever stream it is on
+    if (hipStreamWaitEvent(s, bt->uploaded, 0) != hipSuccess) return PMS_E_DEVICE;
     bt->last = s;
-    if (use_graph) return PMS_E_UNSUPPORTED;  // see the note above enqueue()
-    bt->timed = true;
-    return enqueue(bt, s, true);
+    bt->ran = true;
+    if (!use_graph) {
+        bt->timed = true;
+        const int rc = enqueue(bt, s, true);
+        if (rc) bt->failed = rc;
+        return rc;
+    }
+    bt->timed = false;
+    if (bt->gexec && bt->graph_stream != s) {
+        (void)hipGraphExecDestroy(bt->gexec);
+        bt->gexec = nullptr;
+    }
+    if (!bt->gexec) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return PMS_E_DEVICE;
+        const int rc = enqueue(bt, s, false);
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : PMS_E_DEVICE;
+        }
+        e = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            bt->gexec = nullptr;
+            return PMS_E_DEVICE;
+        }
+        bt->graph_stream = s;
+    }
+    return hip_status(hipGraphLaunch(bt->gexec, s));
 }
 
 int pms_batch_timings(pms_batch* bt, float* ms5) {
@@ -532,48 +658,49 @@ int pms_batch_timings(pms_batch* bt, float* ms5) {
 
 int pms_batch_results(pms_batch* bt, pms_result* outs) {
     if (!bt || (!outs && !bt->hin.empty())) return PMS_E_INVAL;
+    if (bt->failed) return bt->failed;
+    if (!bt->arena || !bt->ran) return PMS_E_INVAL;
     hipStream_t s = bt->last;
-    if (!s) return PMS_E_INVAL;
     const int ni = (int)bt->hin.size();
-    for (int attempt = 0; attempt < 8; attempt++) {
-        if (hipStreamSynchronize(s) != hipSuccess) return PMS_E_DEVICE;
-        std::vector<InstCounters> ctr(ni);
-        if (ni && hipMemcpy(ctr.data(), bt->b.ctr, ni * sizeof(InstCounters),
-                            hipMemcpyDeviceToHost) != hipSuccess)
-            return PMS_E_DEVICE;
-        bool regrow = false;
-        for (int i = 0; i < ni; i++) {
-            if (ctr[i].flags & (kFlagItemOverflow | kFlagNodeOverflow)) return PMS_E_NOMEM;
-            if ((ctr[i].flags & kFlagOutOverflow) || ctr[i].out_count > (unsigned long long)bt->out_cap[i]) {
-                bt->out_cap[i] = next_pow2((int64_t)ctr[i].out_count);
-                regrow = true;
-            }
-        }
-        if (regrow) {
-            // larger output slots: re-plan, re-upload, run again (same result set)
-            void* ws = bt->ext_ws;
-            release_arena(bt);
-            bt->ext_ws = ws;
-            int rc = materialise(bt, false);
-            if (rc) return rc;
-            rc = enqueue(bt, s, true);
-            if (rc) return rc;
-            bt->timed = true;
-            continue;
-        }
-        bt->last_ctr = ctr;
-        const int kw = bt->words;
-        for (int i = 0; i < ni; i++) {
-            const int64_t u = (int64_t)ctr[i].uniq;
-            std::vector<uint64_t> keys((size_t)u * kw);
-            if (u > 0 && hipMemcpy(keys.data(), bt->b.keys + bt->dinst[i].out_off * kw,
-                                   (size_t)u * kw * 8, hipMemcpyDeviceToHost) != hipSuccess)
-                return PMS_E_DEVICE;
-            fill_result(bt->hin[i], keys.data(), u, kw, &outs[i]);
-        }
-        return PMS_OK;
+    for (int i = 0; i < ni; i++) outs[i] = pms_result{};
+    std::vector<InstCounters> ctr(ni);
+    if (ni && hipMemcpyAsync(ctr.data(), bt->b.ctr, ni * sizeof(InstCounters),
+                             hipMemcpyDeviceToHost, s) != hipSuccess)
+        return PMS_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        bt->failed = PMS_E_DEVICE;
+        return PMS_E_DEVICE;
     }
-    return PMS_E_NOMEM;
+    std::vector<int> over;
+    for (int i = 0; i < ni; i++) {
+        if (ctr[i].flags & (kFlagItemOverflow | kFlagNodeOverflow)) return PMS_E_NOMEM;
+        if ((ctr[i].flags & kFlagOutOverflow) || ctr[i].out_count > (unsigned long long)bt->out_cap[i])
+            over.push_back(i);
+    }
+    bt->last_ctr = ctr;
+    const int kw = bt->words;
+    std::vector<std::vector<uint64_t>> keys(ni);
+    for (int i = 0; i < ni; i++) {
+        if (std::find(over.begin(), over.end(), i) != over.end()) continue;
+        const int64_t u = (int64_t)ctr[i].uniq;
+        keys[i].resize((size_t)u * kw);
+        if (u > 0 && hipMemcpyAsync(keys[i].data(), bt->b.keys + bt->dinst[i].out_off * kw,
+                                    (size_t)u * kw * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return PMS_E_DEVICE;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return PMS_E_DEVICE;
+    for (int i = 0; i < ni; i++)
+        if (std::find(over.begin(), over.end(), i) == over.end())
+            fill_result(bt->hin[i], keys[i].data(), (int64_t)ctr[i].uniq, kw, &outs[i]);
+    if (!over.empty()) {
+        // the run's other results stand; only these instances run again
+        int rc = rerun_overflowed(bt, over, ctr, s, outs);
+        if (rc) {
+            for (int i = 0; i < ni; i++) pms_result_free(&outs[i]);
+            return rc;
+        }
+    }
+    return PMS_OK;
 }
 
 int pms_batch_work(pms_batch* bt, int32_t i, pms_work* w) {
@@ -597,9 +724,11 @@ int pms_batch_work(pms_batch* bt, int32_t i, pms_work* w) {
 int pms_batch_destroy(pms_batch* bt) {
     if (!bt) return PMS_OK;
     if (bt->last) (void)hipStreamSynchronize(bt->last);
+    if (bt->own_stream) (void)hipStreamSynchronize(bt->own_stream);
     release_arena(bt);
     for (int i = 0; i < 6; i++)
         if (bt->ev[i]) (void)hipEventDestroy(bt->ev[i]);
+    if (bt->uploaded) (void)hipEventDestroy(bt->uploaded);
     if (bt->own_stream) (void)hipStreamDestroy(bt->own_stream);
     delete bt;
     return PMS_OK;
@@ -611,7 +740,7 @@ int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
     for (int i = 0; i < count; i++) outs[i] = pms_result{};
     if (count == 0) return PMS_OK;
     pms_batch* bt = nullptr;
-    int rc = batch_create_impl(inst, count, tune, nullptr, 0, true, &bt);
+    int rc = batch_create_impl(inst, count, tune, nullptr, 0, true, nullptr, &bt);
     if (rc) return rc;
     rc = pms_batch_run(bt, hip_stream, 0);
     if (!rc) rc = pms_batch_results(bt, outs);

@@ -1,18 +1,23 @@
 // Serving: continuous batching of independent requests (pms_stream_*).
 //
-// Requests are validated and copied on submit, with an estimate of their
-// work: the Appendix D cost model at its best stack size plus the Appendix C
-// expected number of spurious motifs (the output the search must emit and
-// check).  Worker threads repeatedly form a device pass from the queue:
-// requests that have waited longer than kAgeLimit first (oldest first), then
-// the cheapest, admitting a request while the pass's planned device memory
-// plus what other passes hold stays within the stream's cap, and without
-// mixing requests whose estimates differ by more than kMixRatio (a pass lasts
-// as long as its heaviest member).  The pass runs with the batched pipeline
-// (one launch per phase for all its instances).  A request that arrives while
-// a pass is on the device joins a later pass; with more than one worker,
-// passes overlap on the device.  Each ticket's result is the set the instance
-// has alone: instances in a pass never share data.
+// Requests are validated and copied on submit, with their device-memory
+// bound (the batch plan's per-instance bytes) and an estimate of their work:
+// the Appendix D cost model at its best stack size plus the Appendix C
+// expected number of motifs (the output the search must emit and check).
+//
+// Device memory is one pool of device_mem_cap bytes, allocated on the first
+// pass.  Several worker threads (pms_stream_config.workers) each form a
+// device pass from the queue whenever they are free: requests that have
+// waited longer than kAgeLimitS first (oldest first), then the cheapest,
+// admitting a request while the pass's memory bound fits in the pool next to
+// the passes already on the device, and without mixing requests whose
+// estimates differ by more than kMixRatio (a pass lasts as long as its
+// heaviest member).  Each worker runs its pass on its own non-blocking
+// stream in its pool block (a caller workspace of pms_batch_create), so
+// passes overlap on the device: a request that arrives while others run is
+// admitted by the next free worker as soon as memory allows, and its
+// kernels run beside theirs.  Instances in a pass never share data, so each
+// ticket's result is the set the instance has alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +34,7 @@
 #include <vector>
 
 #include "../../include/pms.h"
+#include "pms_internal.h"
 
 namespace {
 
@@ -38,16 +44,16 @@ struct Request {
     std::vector<const char*> ptrs;
     std::string alphabet;
     pms_instance inst{};
-    size_t bytes = 0;     // planned device bytes when run alone
+    size_t bytes = 0;     // device bytes this request adds to a pass (upper bound)
     int status = PMS_E_AGAIN;
     pms_result result{};
-    bool taken = false;   // result handed to the caller
     double est = 0;       // estimated work (arbitrary units, for ordering)
     std::chrono::steady_clock::time_point t_submit;
 };
 
 constexpr double kAgeLimitS = 30.0;  // waited longer: admitted first, oldest first
 constexpr double kMixRatio = 16.0;   // largest / smallest estimate within one pass
+constexpr size_t kAlign = 256;
 
 // |{x : Hd(x, u) <= d}| for one l-mer u over a 4-letter alphabet (Appendix C).
 double ball(int l, int d) {
@@ -73,10 +79,45 @@ double estimate(int n, int m, int l, int d) {
         const double tp = std::exp(std::min(lt + std::log(nd) + (t - 1) * std::log(q), 700.0)) * l;
         best = std::min(best, ts + tp);
     }
-    const double hit = 1.0 - std::pow(1.0 - std::min(1.0, nd / all), (double)r);
-    const double spurious = all * std::pow(hit, (double)n);
-    return best + spurious * l * n * r;
+    return best + pms_expected_motifs(n, m, l, d) * l * n * r;
 }
+
+// First-fit allocator over the stream's device pool (offsets, host-side).
+struct Pool {
+    std::map<size_t, size_t> free_;  // offset -> size
+    void reset(size_t bytes) {
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
 
 }  // namespace
 
@@ -87,32 +128,43 @@ struct pms_stream {
     std::deque<std::shared_ptr<Request>> queue;
     std::map<uint64_t, std::shared_ptr<Request>> all;
     uint64_t next_ticket = 1;
-    size_t held = 0;       // device bytes of passes in flight
-    int inflight = 0;      // instances in flight
+    size_t fixed = 0;        // per-pass bytes independent of its requests
+    void* pool = nullptr;    // device_mem_cap bytes, allocated on first use
+    bool pool_failed = false;
+    Pool alloc;
+    int inflight = 0;        // instances in flight
+    int running = 0;         // passes on the device
     bool stopping = false;
     std::vector<std::thread> workers;
 };
 
 namespace {
 
-size_t pass_bytes(const std::vector<std::shared_ptr<Request>>& reqs, const pms_tune* tune) {
-    std::vector<pms_instance> v;
-    v.reserve(reqs.size());
-    for (auto& r : reqs) v.push_back(r->inst);
-    size_t b = 0;
-    if (pms_batch_workspace_size(v.data(), (int32_t)v.size(), tune, &b) != PMS_OK) return SIZE_MAX;
-    return b;
-}
-
 void worker(pms_stream* s) {
     const pms_tune* tune = &s->cfg.tune;
+    hipStream_t hs = nullptr;
+    if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) hs = nullptr;
     for (;;) {
         std::vector<std::shared_ptr<Request>> pass;
-        size_t bytes = 0;
+        size_t bytes = 0, off = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
-            if (s->queue.empty()) return;  // stopping and nothing queued
+            if (s->queue.empty()) break;  // stopping and nothing queued
+            if (!s->pool && !s->pool_failed) {
+                if (hipMalloc(&s->pool, (size_t)s->cfg.device_mem_cap) != hipSuccess) {
+                    s->pool = nullptr;
+                    s->pool_failed = true;
+                } else {
+                    s->alloc.reset((size_t)s->cfg.device_mem_cap);
+                }
+            }
+            if (!hs || s->pool_failed) {
+                for (auto& r : s->queue) r->status = PMS_E_NOMEM;
+                s->queue.clear();
+                s->cv_done.notify_all();
+                continue;
+            }
             // order: aged requests (oldest first), then the cheapest
             const auto now = std::chrono::steady_clock::now();
             std::vector<std::shared_ptr<Request>> order(s->queue.begin(), s->queue.end());
@@ -126,30 +178,29 @@ void worker(pms_stream* s) {
                                  if (xa) return a->ticket < b->ticket;
                                  return a->est < b->est;
                              });
-            // admit in that order while the pass fits the memory cap
-            const size_t cap = (size_t)s->cfg.device_mem_cap;
+            // admit in that order while the pass's bound fits in the pool
             double lo_est = 0;
+            size_t want = s->fixed;
             for (auto& r : order) {
                 if ((int)pass.size() >= s->cfg.max_wave ||
                     s->inflight + (int)pass.size() >= s->cfg.max_inflight)
                     break;
                 if (!pass.empty() && !aged(r) && r->est > kMixRatio * std::max(lo_est, 1.0)) continue;
-                pass.push_back(r);
-                size_t b = pass_bytes(pass, tune);
-                if (b == SIZE_MAX || s->held + b > cap) {
-                    pass.pop_back();
+                size_t o = 0;
+                if (!s->alloc.alloc(want + r->bytes, &o)) {
                     if (pass.empty()) break;  // the first choice does not fit now
                     continue;
                 }
-                bytes = b;
+                s->alloc.release(o, want + r->bytes);
+                pass.push_back(r);
+                want += r->bytes;
                 if (pass.size() == 1) lo_est = r->est;
             }
-            for (auto& r : pass) s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
             if (pass.empty()) {
                 // the first request in admission order does not fit next to
-                // what is running: wait for a pass to finish (or fail it if
-                // nothing runs)
-                if (s->held == 0) {
+                // what is running: wait for a pass to finish, or fail it if
+                // nothing runs (it is larger than the whole pool)
+                if (s->running == 0) {
                     auto r = order.front();
                     s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
                     r->status = PMS_E_NOMEM;
@@ -159,25 +210,37 @@ void worker(pms_stream* s) {
                 }
                 continue;
             }
-            s->held += bytes;
+            if (!s->alloc.alloc(want, &off)) {  // cannot fail: just probed under the lock
+                s->cv_work.wait(lk);
+                continue;
+            }
+            bytes = want;
+            for (auto& r : pass) s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
             s->inflight += (int)pass.size();
+            s->running++;
         }
         std::vector<pms_instance> v;
         for (auto& r : pass) v.push_back(r->inst);
         std::vector<pms_result> outs(pass.size());
-        int rc = pms_solve_batch(v.data(), (int32_t)v.size(), outs.data(), tune, nullptr);
+        pms_batch* b = nullptr;
+        int rc = pms_batch_create(v.data(), (int32_t)v.size(), tune, (char*)s->pool + off, bytes, &b);
+        if (!rc) rc = pms_batch_run(b, hs, 0);
+        if (!rc) rc = pms_batch_results(b, outs.data());
+        if (b) pms_batch_destroy(b);
         {
             std::lock_guard<std::mutex> lk(s->mu);
             for (size_t i = 0; i < pass.size(); i++) {
                 pass[i]->status = rc;
                 if (rc == PMS_OK) pass[i]->result = outs[i];
             }
-            s->held -= bytes;
+            s->alloc.release(off, bytes);
             s->inflight -= (int)pass.size();
+            s->running--;
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();
     }
+    if (hs) (void)hipStreamDestroy(hs);
 }
 
 int copy_request(const pms_instance* in, Request* r) {
@@ -215,13 +278,13 @@ int pms_stream_create(const pms_stream_config* cfg, pms_stream** out) {
     pms_stream* s = new (std::nothrow) pms_stream();
     if (!s) return PMS_E_NOMEM;
     if (cfg) s->cfg = *cfg;
-    if (s->cfg.device_mem_cap <= 0) s->cfg.device_mem_cap = (int64_t)64 << 30;
+    if (s->cfg.device_mem_cap <= 0) s->cfg.device_mem_cap = (int64_t)32 << 30;
     if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 256;
     if (s->cfg.max_wave <= 0) s->cfg.max_wave = 64;
-    // one device pass at a time by default; PMS_STREAM_WORKERS raises it
-    int workers = 1;
-    if (const char* e = getenv("PMS_STREAM_WORKERS")) workers = std::max(1, std::min(8, atoi(e)));
-    for (int i = 0; i < workers; i++) s->workers.emplace_back(worker, s);
+    if (s->cfg.workers <= 0) s->cfg.workers = 3;
+    s->cfg.workers = std::min(s->cfg.workers, 16);
+    s->fixed = pms::fixed_bytes(&s->cfg.tune);
+    for (int i = 0; i < s->cfg.workers; i++) s->workers.emplace_back(worker, s);
     *out = s;
     return PMS_OK;
 }
@@ -231,12 +294,12 @@ int pms_stream_submit(pms_stream* s, const pms_instance* inst, uint64_t* ticket)
     auto r = std::make_shared<Request>();
     int rc = copy_request(inst, r.get());
     if (rc) return rc;
-    // host-side validation and the instance's own memory plan
+    // host-side validation (the request's own plan)
     size_t b = 0;
     rc = pms_batch_workspace_size(&r->inst, 1, &s->cfg.tune, &b);
     if (rc) return rc;
-    if (b > (size_t)s->cfg.device_mem_cap) return PMS_E_NOMEM;
-    r->bytes = b;
+    r->bytes = pms::inst_bytes(inst->n, inst->m, inst->l, inst->d, &s->cfg.tune);
+    if (s->fixed + r->bytes > (size_t)s->cfg.device_mem_cap) return PMS_E_NOMEM;
     r->est = estimate(r->inst.n, r->inst.m, r->inst.l, r->inst.d);
     r->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
@@ -284,8 +347,10 @@ int pms_stream_destroy(pms_stream* s) {
         s->queue.clear();
     }
     s->cv_work.notify_all();
+    s->cv_done.notify_all();
     for (auto& t : s->workers) t.join();
     for (auto& kv : s->all) pms_result_free(&kv.second->result);
+    if (s->pool) (void)hipFree(s->pool);
     delete s;
     return PMS_OK;
 }

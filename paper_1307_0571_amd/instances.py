@@ -53,12 +53,23 @@ def _mix_np(z: np.ndarray) -> np.ndarray:
     return z
 
 
-class Stream:
-    """Sequential view of one counter-based stream (seed, stream id)."""
+SHAPE_TAG = 0x5348415045  # "SHAPE": keys the per-instance shape draws of batch_mix
 
-    def __init__(self, seed: int, stream: int):
-        self.key = _mix_int((4 * int(seed) + int(stream)) & MASK64)
+
+class Stream:
+    """Sequential view of one counter-based stream (seed, stream id).
+
+    ``Stream.shape(seed)`` is the stream batch_mix draws an instance's
+    (l, d, n, m) from; its key, mix(mix(seed) ^ SHAPE_TAG), is not the key
+    mix(4 * seed' + s) of a planting stream of any seed in use."""
+
+    def __init__(self, seed: int, stream: int, key: int = None):
+        self.key = _mix_int((4 * int(seed) + int(stream)) & MASK64) if key is None else key
         self.i = 0
+
+    @classmethod
+    def shape(cls, seed: int) -> "Stream":
+        return cls(seed, 0, key=_mix_int(_mix_int(int(seed) & MASK64) ^ SHAPE_TAG))
 
     def next(self) -> int:
         self.i += 1
@@ -159,13 +170,14 @@ def batch_mix(seed0: int, count: int,
               n_range=(10, 30), m_range=(300, 1000)) -> List[Instance]:
     """Mixed batch: (l,d) uniform from ``ld``, n and m uniform in the ranges.
 
-    Instance k uses seed ``seed0 + k``; its shape is drawn from stream 3 of a
-    separate shape seed so that the instance bytes depend only on the seed.
+    Instance k uses seed ``seed0 + k``; its shape is drawn from the seed's own
+    shape stream (``Stream.shape``), which no planting stream shares, so the
+    instance bytes depend only on the seed and the shape.
     """
     out = []
     for k in range(count):
         s = seed0 + k
-        sh = Stream(s, 7)
+        sh = Stream.shape(s)
         l, d = ld[sh.below(len(ld))]
         n = n_range[0] + sh.below(n_range[1] - n_range[0] + 1)
         m = m_range[0] + sh.below(m_range[1] - m_range[0] + 1)

@@ -71,7 +71,7 @@ class Work(ctypes.Structure):
 
 class _StreamConfig(ctypes.Structure):
     _fields_ = [("device_mem_cap", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("max_wave", ctypes.c_int32), ("tune", Tune)]
+                ("max_wave", ctypes.c_int32), ("tune", Tune), ("workers", ctypes.c_int32)]
 
 
 _lib = None
@@ -126,6 +126,8 @@ def load():
     lib.pms_strerror.restype = ctypes.c_char_p
     lib.pms_version.restype = ctypes.c_char_p
     lib.pms_default_threshold.argtypes = [ctypes.c_int] * 4
+    lib.pms_expected_motifs.argtypes = [ctypes.c_int] * 4
+    lib.pms_expected_motifs.restype = ctypes.c_double
     lib.pms_device_count.argtypes = [P(ctypes.c_int32)]
     lib.pms_device_synchronize.argtypes = []
     for f in ("pms_solve", "pms_solve_batch", "pms_batch_create", "pms_batch_workspace_size",
@@ -157,6 +159,10 @@ def device_synchronize() -> None:
 
 def default_threshold(n: int, m: int, l: int, d: int) -> int:
     return int(load().pms_default_threshold(n, m, l, d))
+
+
+def expected_motifs(n: int, m: int, l: int, d: int) -> float:
+    return float(load().pms_expected_motifs(n, m, l, d))
 
 
 @dataclass
@@ -285,9 +291,9 @@ class Server:
     """pms_stream_*: continuous batching of submitted instances."""
 
     def __init__(self, device_mem_cap: int = 0, max_inflight: int = 0, max_wave: int = 0,
-                 tune: Optional[Tune] = None):
+                 tune: Optional[Tune] = None, workers: int = 0):
         lib = load()
-        cfg = _StreamConfig(device_mem_cap, max_inflight, max_wave, tune or Tune())
+        cfg = _StreamConfig(device_mem_cap, max_inflight, max_wave, tune or Tune(), workers)
         h = ctypes.c_void_p()
         _check(lib.pms_stream_create(ctypes.byref(cfg), ctypes.byref(h)), "pms_stream_create")
         self.h = h

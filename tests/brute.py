@@ -47,6 +47,20 @@ def motifs_exhaustive(codes: np.ndarray, l: int, d: int, a: int) -> List[tuple]:
     return [tuple(int(x) for x in c) for c in cand]
 
 
+def motifs_from_windows(codes: np.ndarray, l: int, d: int, a: int, lo: int,
+                        hi: int) -> List[tuple]:
+    """The motifs of Section 1's definition that are also within d of one of
+    the S_1 windows lo..hi-1 (the result of the sub-problems of Section 2.3
+    for those windows), over all of Sigma^l."""
+    full = motifs_exhaustive(codes, l, d, a)
+    w = windows(codes[0], l)[lo:hi]
+    if len(full) == 0 or len(w) == 0:
+        return []
+    cand = np.asarray(full, dtype=np.uint8)
+    near = ((cand[:, None, :] != w[None, :, :]).sum(-1) <= d).any(1)
+    return [tuple(int(x) for x in c) for c in cand[near]]
+
+
 def common_neighbours(ts: Sequence[Sequence[int]], budgets: Sequence[int], a: int) -> np.ndarray:
     """All M in Sigma^l with Hd(M, T_i) <= budgets[i] for every i."""
     l = len(ts[0])

@@ -18,6 +18,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_lane_op_model_counts_every_unit():
     sys.path.insert(0, ROOT)
     import bench
-    u = {"t": 3, "filter_tests": 10, "gen_nodes": 100, "verify_tests": 1000}
-    # per node at t = 3: 3*3 budgets + 4*(3 pairs + 1 triple)
-    assert bench.lane_ops(u) == 16 * 10 + (9 + 16) * 100 + 5 * 1000
+    u = {"filter_words": 7, "triple_tests": 10, "gen_nodes": 100, "verify_tests": 1000}
+    # per node at t = 3: 4 * (3 pairs + 1 triple); at t = 4: 4 * (6 + 4)
+    assert bench.lane_ops(u, 3) == 2 * 7 + 14 * 10 + 16 * 100 + 5 * 1000
+    assert bench.lane_ops(u, 4) == 2 * 7 + 14 * 10 + 40 * 100 + 5 * 1000

@@ -1,0 +1,153 @@
+"""GPU path against stored oracle sets on every benchmark configuration.
+
+The stored sets (tests/golden/sets_*.json) were written by
+tests/golden/make_goldens.py, which calls only the CPU oracle and the seeded
+generator.  Each instance is compared by its number of motifs, the SHA-256 of
+the sorted set, and the set itself where it is stored.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1307_0571_amd import instances as I
+from paper_1307_0571_amd import pms
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SERVE_LD = ((9, 2), (11, 3), (13, 4), (15, 5), (17, 6))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _load(group):
+    path = os.path.join(GOLDEN, f"sets_{group}.json")
+    with open(path) as f:
+        return json.load(f)["instances"]
+
+
+def _digest(motifs):
+    h = hashlib.sha256()
+    for x in motifs:
+        h.update(x.encode("ascii") + b"\n")
+    return h.hexdigest()
+
+
+def _check(got, e):
+    assert len(got) == e["count"], (e["seed"], len(got), e["count"])
+    if "motifs" in e:
+        assert got == e["motifs"]
+    assert _digest(got) == e["sha256"]
+    assert e["motif"] in got
+
+
+def _ids(group):
+    try:
+        return [f"{group}_{e['l']}_{e['d']}_seed{e['seed']}" for e in _load(group)]
+    except OSError:
+        return []
+
+
+def _entries(group):
+    try:
+        return _load(group)
+    except OSError:
+        return []
+
+
+def _solve(inst, tune=None):
+    return pms.solve_batch([pms.Problem(inst.seqs, inst.l, inst.d)], tune=tune)[0]
+
+
+@pytest.mark.parametrize("e", _entries("plain"), ids=_ids("plain"))
+def test_plain_config(e):
+    """Plain single instances (9,2), (13,4), (15,5), n=20, m=600, seeds 0-4."""
+    _say(f"plain ({e['l']},{e['d']}) seed={e['seed']}")
+    inst = I.planted(e["seed"], e["l"], e["d"], e["n"], e["m"])
+    _check(_solve(inst), e)
+
+
+@pytest.mark.parametrize("e", _entries("large"), ids=_ids("large"))
+def test_large_17_6_config(e):
+    """(17,6), n=20, m=600, seeds 0-2."""
+    _say(f"large ({e['l']},{e['d']}) seed={e['seed']}")
+    inst = I.planted(e["seed"], e["l"], e["d"], e["n"], e["m"])
+    _check(_solve(inst), e)
+
+
+def _is_motif(seqs, mot, d):
+    code = {c: i for i, c in enumerate("ACGT")}
+    M = np.array([code[c] for c in mot], dtype=np.int8)
+    l = len(mot)
+    for s in seqs:
+        a = np.array([code[c] for c in s], dtype=np.int8)
+        win = np.lib.stride_tricks.sliding_window_view(a, l)
+        if int((win != M).sum(axis=1).min()) > d:
+            return False
+    return True
+
+
+def test_batched_config_256():
+    """The whole 256-instance mixed batch ((11,3)/(13,4)/(15,5), n 10-30,
+    m 300-1000) in one device pass: the 32 stored instances (a seeded sample
+    plus the four with the most expected motifs) equal the oracle's sets,
+    every instance reports its planted motif, and a sample of reported
+    motifs satisfies the definition directly."""
+    stored = _load("batched")
+    insts = I.batch_mix(1000, 256)
+    _say("batched: 256 instances in one pass")
+    got = pms.solve_batch([pms.Problem(x.seqs, x.l, x.d) for x in insts])
+    for e in stored:
+        x = insts[e["index"]]
+        assert (x.seed, x.l, x.d, x.n, x.m) == (e["seed"], e["l"], e["d"], e["n"], e["m"])
+        _check(got[e["index"]], e)
+    rng = np.random.default_rng(5)
+    for x, g in zip(insts, got):
+        assert x.motif in g, x.seed
+        for k in rng.choice(len(g), size=min(3, len(g)), replace=False):
+            assert _is_motif(x.seqs, g[int(k)], x.d), (x.seed, g[int(k)])
+
+
+def test_batched_sample_alone_equals_in_batch():
+    """The stored batched instances solved as their own batch and one by one
+    give the same sets as in the full batch (their stored sets)."""
+    stored = _load("batched")[:8]
+    insts = I.batch_mix(1000, 256)
+    xs = [insts[e["index"]] for e in stored]
+    _say("batched sample: as a batch of 8 and alone")
+    got = pms.solve_batch([pms.Problem(x.seqs, x.l, x.d) for x in xs])
+    for g, e, x in zip(got, stored, xs):
+        _check(g, e)
+        _check(_solve(x), e)
+
+
+def test_serving_config_sample():
+    """The stored sample of the 10,000-request served stream ((9,2) ..
+    (17,6), n 10-30, m 200-1000), submitted interleaved with the first 24
+    requests of the stream to a server with three overlapping workers: each
+    stored request's served set equals the oracle's, and every request
+    reports its planted motif."""
+    stored = _load("serving")
+    stream = I.batch_mix(2000, 10000, ld=SERVE_LD, m_range=(200, 1000))
+    order = list(range(24)) + [e["index"] for e in stored]
+    _say(f"serving: {len(order)} requests, 3 workers")
+    srv = pms.Server(workers=3)
+    try:
+        tickets = {k: srv.submit(pms.Problem(stream[k].seqs, stream[k].l, stream[k].d))
+                   for k in order}
+        got = {k: srv.wait(t) for k, t in tickets.items()}
+    finally:
+        srv.close()
+    for e in stored:
+        x = stream[e["index"]]
+        assert (x.seed, x.l, x.d, x.n, x.m) == (e["seed"], e["l"], e["d"], e["n"], e["m"])
+        _check(got[e["index"]], e)
+    for k in order:
+        assert stream[k].motif in got[k]

@@ -103,36 +103,138 @@ def test_device_batch_rerun():
         b.close()
 
 
-@pytest.mark.skip(reason="asynchronous back-to-back launches and hipGraph replay faulted once "
-                         "and stalled three times on the GPU; the path is switched off "
-                         "(pms_batch_run returns PMS_E_UNSUPPORTED for graphs) until the "
-                         "cause is shown")
 def test_graph_replay():
+    """hipGraph capture of the pipeline, replayed several times with eager
+    runs, host synchronisation and result reads between the replays; every
+    replay must give the oracle's sets."""
+    _say("hipGraph capture and replay")
     insts = [I.planted(s, 10, 2, 10, 200) for s in range(3)]
     want = [oracle.solve_b(x.seqs, 10, 2) for x in insts]
     b = pms.Batch([pms.Problem(x.seqs, x.l, x.d) for x in insts])
     try:
-        for graph in (True, True):
+        for graph in (True, False, True, True, False, True):
             b.run(graph=graph)
-            assert b.results() == want
+            assert b.results() == want, graph
     finally:
         b.close()
 
 
-def test_caller_workspace():
-    _say("caller-provided workspace")
-    inst = I.planted(5, 9, 2, 12, 250)
-    want = oracle.solve_a(inst.seqs, 9, 2)
-    probs = [pms.Problem(inst.seqs, 9, 2)]
-    size = pms.Batch.workspace_size(probs)
-    # a first batch owns device memory; a second borrows a sub-range of it
-    owner = pms.Batch(probs)
+def test_graph_replay_on_borrowed_stream():
+    _say("hipGraph replay on a caller stream")
+    from . import hip_rt
+    inst = I.planted(8, 11, 3, 12, 300)
+    want = oracle.solve_b(inst.seqs, 11, 3)
+    st = hip_rt.stream_create()
+    b = pms.Batch([pms.Problem(inst.seqs, 11, 3)])
     try:
-        owner.run()
-        assert owner.results() == [want]
+        for _ in range(3):
+            b.run(stream=st, graph=True)
+            assert b.results() == [want]
     finally:
-        owner.close()
-    assert size > 0
+        b.close()
+        hip_rt.stream_destroy(st)
+
+
+def test_caller_workspace():
+    """A batch borrows a caller-allocated device workspace of exactly
+    pms_batch_workspace_size bytes; one byte less is refused before any
+    device work."""
+    _say("caller-provided workspace")
+    from . import hip_rt
+    insts = [I.planted(5, 9, 2, 12, 250), I.planted(6, 11, 3, 10, 300)]
+    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+    want = [oracle.solve_a(x.seqs, x.l, x.d) for x in insts]
+    size = pms.Batch.workspace_size(probs)
+    ws = hip_rt.malloc(size)
+    try:
+        hip_rt.memset(ws, 0xA5, size)  # stale contents must not matter
+        with pytest.raises(pms.PmsError) as e:
+            pms.Batch(probs, workspace=(ws, size - 1))
+        assert e.value.status == pms.PMS_E_NOMEM
+        b = pms.Batch(probs, workspace=(ws, size))
+        try:
+            for _ in range(2):
+                b.run()
+                assert b.results() == want
+        finally:
+            b.close()
+    finally:
+        hip_rt.device_synchronize()
+        hip_rt.free(ws)
+
+
+def test_caller_workspace_small_output_slots():
+    """Output slots smaller than the set (out_capacity 1) with a caller
+    workspace: the overflowing instance is solved again alone in library
+    memory and the result is still exact."""
+    _say("caller workspace, overflowing output slots")
+    from . import hip_rt
+    inst = I.planted(9, 9, 2, 6, 300)
+    want = oracle.solve_a(inst.seqs, 9, 2)
+    assert len(want) > 1
+    probs = [pms.Problem(inst.seqs, 9, 2)]
+    tune = pms.Tune(out_capacity=1)
+    size = pms.Batch.workspace_size(probs, tune)
+    ws = hip_rt.malloc(size)
+    try:
+        b = pms.Batch(probs, tune=tune, workspace=(ws, size))
+        try:
+            b.run()
+            assert b.results() == [want]
+        finally:
+            b.close()
+    finally:
+        hip_rt.device_synchronize()
+        hip_rt.free(ws)
+
+
+def test_pms_solve_c_entry_and_borrowed_stream():
+    """pms_solve itself (the single-instance C entry point), and
+    pms_solve_batch on a caller-created stream."""
+    _say("pms_solve and a borrowed hip stream")
+    import ctypes
+    from . import hip_rt
+    inst = I.planted(12, 10, 2, 9, 240)
+    want = oracle.solve_a(inst.seqs, 10, 2)
+    lib = pms.load()
+    enc = [s.encode() for s in inst.seqs]
+    arr = (ctypes.c_char_p * len(enc))(*enc)
+    res = pms._Result()
+    assert lib.pms_solve(arr, len(enc), inst.m, b"ACGT", 10, 2, ctypes.byref(res)) == pms.PMS_OK
+    assert res.words == 1 and res.l == 10
+    assert pms._take(res) == want
+    st = hip_rt.stream_create()
+    try:
+        got = pms.solve_batch([pms.Problem(inst.seqs, 10, 2)], stream=st)
+        assert got == [want]
+        b = pms.Batch([pms.Problem(inst.seqs, 10, 2)])
+        try:
+            b.run(stream=st)
+            assert b.results() == [want]
+        finally:
+            b.close()
+    finally:
+        hip_rt.stream_destroy(st)
+
+
+# Sizes at the limits of the batched and served configurations: up to 30 and
+# 32 strings, strings of 1000 characters, 2048 windows per string (32 words
+# per row bitset), and 2d >= l (every pair of l-mers compatible).
+@pytest.mark.parametrize("name,seed,l,d,n,m", [
+    ("n30_m1000", 40, 9, 2, 30, 1000),
+    ("n32", 41, 9, 2, 32, 400),
+    ("n31_m1000_11_3", 42, 11, 3, 31, 1000),
+    ("r2048", 43, 9, 1, 3, 2056),
+    ("2d_ge_l_6_3", 44, 6, 3, 5, 60),
+    ("2d_ge_l_7_4", 45, 7, 4, 3, 40),
+])
+def test_limit_sizes_vs_oracle(name, seed, l, d, n, m):
+    _say(f"{name}: seed={seed} l={l} d={d} n={n} m={m}")
+    inst = I.planted(seed, l, d, n, m)
+    want = oracle.solve_a(inst.seqs, l, d)
+    got = _gpu(inst)
+    assert got == want
+    assert inst.motif in got
 
 
 def test_serving_matches_alone():

@@ -63,6 +63,31 @@ def test_exhaustive_fuzz(oracle_lib):
             assert got_b == want, (case, a, l, d, n, m, t)
 
 
+@pytest.mark.parametrize("l,d,n,m,seed", [(6, 1, 12, 200, 30), (7, 2, 8, 90, 31),
+                                         (8, 2, 6, 120, 32), (5, 1, 4, 33, 33)])
+def test_windows_restriction_bruteforce(oracle_lib, l, d, n, m, seed):
+    """oracle_b restricted to S_1 windows [lo, hi) (Section 2.3 sub-problems)
+    equals the exhaustive motif set filtered to motifs within d of one of
+    those windows, for ranges at both ends, in the middle, single windows and
+    empty ranges; the union over a partition of [0, r) is the whole set."""
+    inst = I.planted(seed, l, d, n, m)
+    r = m - l + 1
+    rng = random.Random(seed)
+    cuts = sorted({0, r, *(rng.randint(1, r - 1) for _ in range(3))})
+    ranges = list(zip(cuts[:-1], cuts[1:])) + [(0, 1), (r - 1, r), (5, 5), (r // 2, r // 2 + 1)]
+    whole = set()
+    for lo, hi in ranges:
+        want = _tuples_to_str(brute.motifs_from_windows(inst.codes, l, d, 4, lo, hi), "ACGT")
+        for t in (1, 2, 3):
+            got = oracle_lib.solve_b(inst.seqs, l, d, t=t, windows=(lo, hi))
+            assert got == want, (lo, hi, t)
+        if (lo, hi) in zip(cuts[:-1], cuts[1:]):
+            whole |= set(want)
+    full = _tuples_to_str(brute.motifs_exhaustive(inst.codes, l, d, 4), "ACGT")
+    assert sorted(whole) == full
+    assert oracle_lib.solve_b(inst.seqs, l, d, windows=(0, r)) == full
+
+
 def test_golden_hand_examples(oracle_lib):
     """Hand-worked instances (tests/golden/hand_examples.json)."""
     with open(os.path.join(GOLDEN, "hand_examples.json")) as f:
