@@ -199,6 +199,38 @@ int pms_stream_wait(pms_stream* s, uint64_t ticket, pms_result* out, int64_t tim
 /* Finishes in-flight work, fails queued tickets with PMS_E_ABORTED, frees. */
 int pms_stream_destroy(pms_stream* s);
 
+/* ---- allocation-free variant of pms_solve ----
+ * For callers that cannot allocate device memory: code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Solves
+ * one instance with every intermediate buffer in a fixed device array of
+ * the library (pms_noalloc_scratch_bytes() = 256 MiB per GPU, held from the
+ * first call on that GPU until the process ends); calls no hipMalloc,
+ * hipFree or other allocating routine and enqueues only kernels (no memset
+ * or copy) on hip_stream (NULL = the legacy default stream), then returns
+ * without waiting.
+ *   chars     device, n*m characters, string i at chars + i*m (no
+ *             terminators); caller-owned, read until the stream reaches the
+ *             end of this call's work.
+ *   alphabet  host string of exactly 4 distinct characters (DNA "ACGT");
+ *             codes by ascending byte value, as for pms_solve.
+ *   keys_out  device, keys_cap * words uint64 (words = 1 if l <= 32, else 2):
+ *             receives the sorted motif set as pms_result.packed lays it out.
+ *   count_out device int64: the number of motifs, or a negative pms_status:
+ *             PMS_E_ALPHABET (a window holds a character outside the
+ *             alphabet), PMS_E_NOMEM (more motifs than keys_cap, or more
+ *             emitted motifs than the scratch's key slots).
+ * Returns PMS_E_INVAL / PMS_E_ALPHABET / PMS_E_UNSUPPORTED as pms_solve does
+ * for bad arguments, PMS_E_NOMEM when the instance's buffers do not fit in
+ * the scratch array (nothing is enqueued then), PMS_E_DEVICE on a launch
+ * error.  Every call on one GPU uses the same scratch and leaves its
+ * contents there; calls that overlap on one GPU (other streams, threads)
+ * race and must be serialised by the caller. */
+int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t m, const char* alphabet,
+                             int32_t l, int32_t d, uint64_t* keys_out, int64_t keys_cap,
+                             int64_t* count_out, void* hip_stream);
+/* Size of that scratch array in bytes (host-only). */
+size_t pms_noalloc_scratch_bytes(void);
+
 /* Appendix D cost-model threshold the library uses when tune.threshold is 0
  * (a stack size in [2, 8]); host-only. */
 int pms_default_threshold(int n, int m, int l, int d);

@@ -55,6 +55,7 @@ struct InstCounters {
 constexpr unsigned kFlagOutOverflow = 1u;
 constexpr unsigned kFlagItemOverflow = 2u;
 constexpr unsigned kFlagNodeOverflow = 4u;
+constexpr unsigned kFlagBadChar = 8u;  // a window holds a character outside the alphabet
 
 // Global queue counters.
 struct QueueCounters {

@@ -97,11 +97,14 @@ __global__ void k_fill_parts(uint64_t* parts, unsigned long long n) {
 
 // ---------------------------------------------------------------- pack (a1)
 
+// A character outside the alphabet (table entry 0xFF) sets kFlagBadChar;
+// the host path has rejected those already, device-resident inputs have not.
 template <int W>
 __global__ __launch_bounds__(256) void k_pack(const InstDev* __restrict__ insts,
                                               const uint8_t* __restrict__ chars,
                                               const uint8_t* __restrict__ lut,
-                                              Lm<W>* __restrict__ lmers) {
+                                              Lm<W>* __restrict__ lmers,
+                                              InstCounters* __restrict__ ctr) {
     typedef typename MaskOf<W>::type M;
     const InstDev I = insts[blockIdx.y];
     const int N = I.n * I.r;
@@ -111,11 +114,14 @@ __global__ __launch_bounds__(256) void k_pack(const InstDev* __restrict__ insts,
     const uint8_t* p = chars + I.chars_off + (int64_t)row * I.m + w;
     const uint8_t* tab = lut + (int64_t)blockIdx.y * 256;
     M h = 0, lo = 0;
+    bool bad = false;
     for (int i = 0; i < I.l; i++) {
         uint32_t c = tab[p[i]];
+        bad |= c == 0xFFu;
         h |= (M)((c >> 1) & 1u) << i;
         lo |= (M)(c & 1u) << i;
     }
+    if (bad) atomicOr(&ctr[blockIdx.y].flags, kFlagBadChar);
     Lm<W> v;
     v.h = h;
     v.lo = lo;
@@ -1029,10 +1035,10 @@ hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream
     dim3 grid((p.max_n_lmers + 255) / 256, p.n_inst);
     if (p.words == 1)
         hipLaunchKernelGGL(k_pack<1>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
-                           (Lm<1>*)b.lmers);
+                           (Lm<1>*)b.lmers, b.ctr);
     else
         hipLaunchKernelGGL(k_pack<2>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
-                           (Lm<2>*)b.lmers);
+                           (Lm<2>*)b.lmers, b.ctr);
     return hipGetLastError();
 }
 

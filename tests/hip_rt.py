@@ -24,8 +24,9 @@ def _rt():
         _hip.hipStreamSynchronize.argtypes = [vp]
         _hip.hipMemset.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
         _hip.hipDeviceSynchronize.argtypes = []
+        _hip.hipMemcpy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
         for f in ("hipMalloc", "hipFree", "hipStreamCreateWithFlags", "hipStreamDestroy",
-                  "hipStreamSynchronize", "hipMemset", "hipDeviceSynchronize"):
+                  "hipStreamSynchronize", "hipMemset", "hipDeviceSynchronize", "hipMemcpy"):
             getattr(_hip, f).restype = ctypes.c_int
     return _hip
 
@@ -47,6 +48,17 @@ def free(ptr: int) -> None:
 
 def memset(ptr: int, value: int, nbytes: int) -> None:
     _check(_rt().hipMemset(ctypes.c_void_p(ptr), value, nbytes), "hipMemset")
+
+
+def copy_to_device(dst: int, data: bytes) -> None:
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(_rt().hipMemcpy(ctypes.c_void_p(dst), buf, len(data), 1), "hipMemcpy H2D")
+
+
+def copy_from_device(src: int, nbytes: int) -> bytes:
+    buf = ctypes.create_string_buffer(nbytes)
+    _check(_rt().hipMemcpy(buf, ctypes.c_void_p(src), nbytes, 2), "hipMemcpy D2H")
+    return buf.raw
 
 
 def stream_create() -> int:
