@@ -99,6 +99,11 @@ typedef struct pms_tune {
                                one of those windows.  0, 0 = every window;
                                end beyond the last window is clamped;
                                begin > end (end > 0) is PMS_E_INVAL */
+    int32_t stage_cap;      /* survivors of the remaining strings staged in LDS
+                               for one tail batch (512..4096, rounded up to a
+                               multiple of 64; 0 = by the batch's sizes);
+                               larger sets are checked from the level bitsets */
+    int32_t pad0;
     int64_t out_capacity;   /* motif slots per instance (before removal of
                                repeats); 0 = sized from the Appendix C expected
                                number of motifs (pms_expected_motifs) */

@@ -13,12 +13,9 @@ constexpr int kMaxN = 32;        // strings per instance (row bit masks are 32-b
 constexpr int kMaxR = 2048;      // windows per string (11-bit window index)
 constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes)
 constexpr int kMaxT = 8;         // stack size at which generation starts
-constexpr int kVCap = 512;       // survivor l-mers staged in LDS for verification
-constexpr int kCandCap = 128;    // candidate buffer in LDS
-constexpr int kNodeBatch = 16;   // generator nodes expanded per wave step (x4 children)
-constexpr int kNodeCap = 4 * kNodeBatch * kMaxL;  // node stack bound per wave (see search)
-constexpr int kRing = 128;       // top of the node stack kept in LDS (power of two, >= 128)
 constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
+constexpr int kStageCapMin = 512;   // staged survivors of one tail batch (LDS entries)
+constexpr int kStageCapMax = 4096;
 constexpr int kMaxInst = 1 << 21;  // instances per batch (21-bit field of a work item)
 
 // Work item (64 bits): inst << 43 | lo << 32 | u1 << 16 | p2 << 11 | x2.
@@ -54,7 +51,7 @@ struct InstCounters {
 
 constexpr unsigned kFlagOutOverflow = 1u;
 constexpr unsigned kFlagItemOverflow = 2u;
-constexpr unsigned kFlagNodeOverflow = 4u;
+constexpr unsigned kFlagNodeOverflow = 4u;  // a search loop reached its step guard
 constexpr unsigned kFlagBadChar = 8u;  // a window holds a character outside the alphabet
 
 // Global queue counters.
@@ -63,12 +60,6 @@ struct QueueCounters {
     unsigned long long item_next;   // next item to take
     unsigned long long item_cap;
     unsigned long long pad;
-};
-
-// Generator node: prefix bit-planes, budgets (one byte per stack member), depth.
-struct Node {
-    uint64_t h, lo, bud;
-    uint32_t depth, pad;
 };
 
 struct LaunchPlan {
@@ -82,7 +73,7 @@ struct LaunchPlan {
     int search_blocks;   // persistent grid size
     int compat_kernel;   // 1 VALU
     int split;           // third stack members one work item keeps
-    int max_out_keys_lds;
+    int s2cap;           // staged survivors per tail batch (multiple of 64)
 };
 
 // Device buffers of one planned batch.
@@ -94,7 +85,6 @@ struct DevBufs {
     uint64_t* compat;
     uint64_t* items;
     uint64_t* parts;     // part items (second search launch)
-    Node* nodes;
     uint64_t* keys;
     InstCounters* ctr;
     QueueCounters* q;    // q[0]: items, q[1]: parts

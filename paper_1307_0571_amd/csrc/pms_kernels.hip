@@ -257,6 +257,39 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
 }
 
 // --------------------------------------------------------------- search
+//
+// One persistent wave per work item runs Algorithm 2 depth-first from the
+// item's stack {u1, u2}: per-level row bitsets in LDS, the pair bit and the
+// Theorem 1 filter on every push, the smallest remaining string next.
+//
+// The last level is a "tail batch".  When the stack holds t-1 members and
+// the next member comes from string p, every candidate of p (up to
+// kTailSlots at a time) becomes a slot:
+//   * the survivors of the other remaining strings are staged once in LDS
+//     (one segment per string, fewest survivors first), and each slot keeps
+//     one bit per staged l-mer: the push filter of its candidate (Hd <= 2d
+//     and Theorem 1 against every stack member), evaluated on the staged
+//     l-mers directly;
+//   * the pruned trees of Algorithm 1 of all live slots are split into
+//     subtrees at depth 2 or 3 and handed to lanes; each lane walks its
+//     subtree depth-first on its own (no shared stack): a node's 4-bit mask
+//     of valid children comes from the budgets of the prefix and the pair /
+//     triple slacks of the suffix (the prune of Algorithm 1 with Theorem 1),
+//     and the unvisited children of every depth on the path are kept as
+//     nibbles in registers;
+//   * complete l-mers go to an LDS buffer and are checked lane by lane
+//     against the slot's staged survivors of every remaining string
+//     (Algorithm 2's isMotif on the filtered rows).
+// When the staged survivors do not fit the LDS area, the slots keep no
+// bits and their l-mers are checked against the level bitsets directly
+// (still exact: every l-mer within d of a common d-neighbour of the stack
+// passes the pair and Theorem 1 tests).  A complete stack (t reached at a
+// push, no string left, or a single string) is a tail batch of one slot.
+
+constexpr int kTailSlots = 16;  // candidates of one tail batch (<= 32: one bit each)
+constexpr int kLeafCap = 256;   // generated l-mers awaiting the check
+constexpr int kListCap = 512;   // filter listing entries per pass (lives in the staging area)
+constexpr long long kStepLimit = 1ll << 32;  // guard on every loop of the tail batch
 
 template <int W, int TMAX>
 struct SearchLds {
@@ -266,14 +299,14 @@ struct SearchLds {
     Lm<W> st[TMAX];                  // the stack
     typename MaskOf<W>::type E[TMAX][TMAX];  // e(s_a, s_b) differing-position masks
     int HD[TMAX][TMAX];              // Hd(s_a, s_b)
-    typename MaskOf<W>::type rh[kRing], rl[kRing];  // generator node ring: prefix planes
-    uint8_t rd[kRing];                               // and depth
-    Lm<W> cand[kCandCap];            // complete common neighbours awaiting the check
-    Lm<W> vset[kVCap];               // staged survivors (verification)
-    uint16_t voff[kMaxN + 1];        // segment g of vset: [voff[g], voff[g+1])
-    uint16_t rowbase[kMaxN];         // first vset slot of string j's segment
-    int nseg;                        // staged segments (remaining strings)
+    uint16_t segoff[kMaxN + 1];      // staged segment g: [segoff[g], segoff[g+1])
+    uint8_t segrow[kMaxN];           // string of segment g
+    int nseg;
     int item;
+    int xs[kTailSlots];              // window of each slot's candidate
+    int aslot[kTailSlots];           // live slots, in order
+    typename MaskOf<W>::type dq_h[64], dq_l[64];  // donated subtrees: prefix planes,
+    uint8_t dq_d[64], dq_s[64];                   // depth and slot
 };
 
 template <int W>
@@ -287,9 +320,26 @@ __device__ __forceinline__ uint64_t key_word(uint64_t h, uint64_t lo, int from, 
     return k;
 }
 
+// bits at positions < s (s <= 64)
+__device__ __forceinline__ uint32_t low_bits(uint32_t, int s) { return s >= 32 ? ~0u : ((1u << s) - 1u); }
+__device__ __forceinline__ uint64_t low_bits(uint64_t, int s) { return s >= 64 ? ~0ull : ((1ull << s) - 1ull); }
+
+// 4-bit child mask from a pair's or triple's slack: child c is kept when
+// slack >= (members) - (members whose character at the position is c).
+__device__ __forceinline__ uint32_t slack2(int s, uint32_t oa, uint32_t ob) {
+    return s >= 2 ? 0xFu : s == 1 ? (oa | ob) : s == 0 ? (oa & ob) : 0u;
+}
+__device__ __forceinline__ uint32_t slack3(int s, uint32_t oa, uint32_t ob, uint32_t oc) {
+    return s >= 3 ? 0xFu
+         : s == 2 ? (oa | ob | oc)
+         : s == 1 ? ((oa & ob) | (oa & oc) | (ob & oc))
+         : s == 0 ? (oa & ob & oc) : 0u;
+}
+
 template <int W, int TMAX>
 struct Searcher {
     typedef typename MaskOf<W>::type M;
+    static constexpr int NW = W == 1 ? 2 : 4;  // u64 words of child nibbles (16 depths each)
     SearchLds<W, TMAX>& S;
     uint64_t* lv;  // LDS level bitsets: level k at lv + (k - 2) * level_words
     int level_words;
@@ -298,12 +348,29 @@ struct Searcher {
     const Lm<W>* L;       // this instance's l-mers
     const uint64_t* C;    // this instance's compat matrix
     uint64_t u1g;         // global id of the level-1 l-mer (string 0)
-    Node* nodes;          // this wave's generator stack
     uint64_t* keys;
     InstCounters* ctr;
     int lane;
+    unsigned* cntw;
+    int inv_bw;           // ceil(65536 / bw)
+    Lm<W>* s2;            // staged survivors (and the filter's listing scratch)
+    uint64_t* memb;       // [kTailSlots][mw] survivor bits per slot
+    Lm<W>* ut;            // [kTailSlots] candidate of each slot
+    Lm<W>* leaf;          // [kLeafCap] generated l-mers
+    uint8_t* leafslot;    // [kLeafCap] their slots
+    int s2cap, mw;        // staging area (entries of sizeof(Lm<W>)), survivor-bit words per slot
+    bool half;            // W == 1 and l <= 16: staged l-mers packed in 4 bytes
+    int scap;             // staged l-mers that fit
 
-    __device__ uint64_t* level(int k) { return lv + (k - 2) * level_words; }
+    __device__ __forceinline__ uint64_t* level(int k) { return lv + (k - 2) * level_words; }
+    __device__ __forceinline__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
+    __device__ __forceinline__ unsigned cnt16(int k, int j) { return cntw[k * kMaxN + j]; }
+
+    // string index of flattened row word i (i < n * bw <= 1024): an exact
+    // reciprocal multiply instead of a division
+    __device__ __forceinline__ int row_of(int i) const {
+        return (int)(((unsigned)i * (unsigned)inv_bw) >> 16);
+    }
 
     // Push the window px of string prow as stack member k (stack size becomes
     // k + 1) and filter every remaining string's survivors into level k + 1:
@@ -311,7 +378,7 @@ struct Searcher {
     // s_a, Cd(s_a, top, v) <= 3d (Theorem 1 with d1 = d2 = d3 = d; its pair
     // conditions already hold).  Returns whether every remaining string still
     // has a survivor (Algorithm 2's R'.size > 0).
-    __device__ bool push_filter(int k, int prow, int px) {
+    __device__ __forceinline__ bool push_filter(int k, int prow, int px) {
         const int n = I.n, bw = I.bw, r = I.r;
         const int ug = prow * r + px;
         const Lm<W> top = L[ug];
@@ -336,18 +403,12 @@ struct Searcher {
         return ballot(bad) == 0ull;
     }
 
-    // string index of flattened row word i (i < n * bw <= 1024): an exact
-    // reciprocal multiply instead of a division
-    __device__ __forceinline__ int row_of(int i) const {
-        return (int)(((unsigned)i * (unsigned)inv_bw) >> 16);
-    }
-
     // Lanes over the row words of the remaining strings: child = parent AND
     // compat(top).  With the Theorem 1 filter, the set bits of each block of
-    // 64 words are listed in LDS (the staging buffer, kVCap entries per
-    // pass: l-mer index and word/bit) by a wave prefix sum, lanes then test
-    // one listed survivor each (independent l-mer loads) and clear the
-    // failures with an LDS atomic AND.  Counts are taken afterwards.
+    // 64 words are listed in LDS (kListCap entries per pass: l-mer index and
+    // word/bit) by a wave prefix sum, lanes then test one listed survivor
+    // each (independent l-mer loads) and clear the failures with an LDS
+    // atomic AND.  Counts are taken afterwards.
     template <typename PP>
     __device__ __forceinline__ void filter_body(PP parent, const uint64_t* Cu, const Lm<W>& top,
                                                 int k, uint32_t rows) {
@@ -376,38 +437,51 @@ struct Searcher {
             const int incl = wave_incl_scan(c);
             const int T = __shfl(incl, 63, 64);
             const int w = i - j * bw;
-            for (int lo = 0; lo < T; lo += kVCap) {
-                // list the bits of rank [lo, lo + kVCap) of this block
+            for (int lo = 0; lo < T; lo += kListCap) {
+                // list the bits of rank [lo, lo + kListCap) of this block
                 int rank = incl - c;
                 uint64_t bits = nb;
-                while (bits && rank < lo + kVCap) {
+                while (bits && rank < lo + kListCap) {
                     const int bb = __builtin_ctzll(bits);
                     bits &= bits - 1;
                     if (rank >= lo) {
-                        S.vset[rank - lo].h = (M)(j * r + w * 64 + bb);
-                        S.vset[rank - lo].lo = (M)((i << 6) | bb);
+                        s2[rank - lo].h = (M)(j * r + w * 64 + bb);
+                        s2[rank - lo].lo = (M)((i << 6) | bb);
                     }
                     rank++;
                 }
                 __syncthreads();
-                const int cnt = T - lo < kVCap ? T - lo : kVCap;
-                for (int q0 = 0; q0 < cnt; q0 += 64) {
-                    const int q = q0 + lane;
-                    if (q < cnt) {
-                        const int g = (int)S.vset[q].h;
-                        const int e = (int)S.vset[q].lo;
-                        const Lm<W> v = L[g];
-                        const int hv = pc(dmask(top, v));
+                const int cnt = T - lo < kListCap ? T - lo : kListCap;
+                // four listed survivors per lane per round: their l-mer loads
+                // are independent and in flight together
+                for (int q0 = 0; q0 < cnt; q0 += 256) {
+                    Lm<W> v[4];
+                    int e[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int q = q0 + 64 * u + lane;
+                        e[u] = -1;
+                        v[u].h = 0;
+                        v[u].lo = 0;
+                        if (q < cnt) {
+                            e[u] = (int)s2[q].lo;
+                            v[u] = L[(int)s2[q].h];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (e[u] < 0) continue;
+                        const int hv = pc(dmask(top, v[u]));
                         bool ok = true;
 #pragma unroll
                         for (int a = 0; a < TMAX; a++) {
                             if (a < k) {
-                                const M da = dmask(sa[a], v);
+                                const M da = dmask(sa[a], v[u]);
                                 ok &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
                             }
                         }
                         if (!ok)
-                            atomicAnd((unsigned long long*)&child[e >> 6], ~(1ull << (e & 63)));
+                            atomicAnd((unsigned long long*)&child[e[u] >> 6], ~(1ull << (e[u] & 63)));
                     }
                 }
                 __syncthreads();
@@ -424,13 +498,7 @@ struct Searcher {
         }
     }
 
-    // counts live in 32-bit LDS words for atomics; cnt16 reads them back
-    __device__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
-    __device__ unsigned cnt16(int k, int j) { return cntw[k * kMaxN + j]; }
-    unsigned* cntw;
-    int inv_bw;  // ceil(65536 / bw)
-
-    __device__ int choose_row(int k) {
+    __device__ __forceinline__ int choose_row(int k) {
         const uint32_t rows = S.rows[k];
         int v = 0x7FFFFFFF;
         if (lane < I.n && ((rows >> lane) & 1u)) v = (int)(cnt16(k, lane) << 5) | lane;
@@ -441,7 +509,7 @@ struct Searcher {
     // window of the survivor of rank nth (0-based) of string p at level k,
     // or -1 if the string has no more survivors; lanes hold one word each
     // (bw <= 32)
-    __device__ int nth_bit(int k, int p, int nth) {
+    __device__ __forceinline__ int nth_bit(int k, int p, int nth) {
         const uint64_t* row = level(k) + p * I.bw;
         const uint64_t w = lane < I.bw ? row[lane] : 0ull;
         const int c = pc(w);
@@ -459,7 +527,7 @@ struct Searcher {
     }
 
     // next survivor of string p at level k with window >= from, or -1
-    __device__ int next_bit(int k, int p, int from) {
+    __device__ __forceinline__ int next_bit(int k, int p, int from) {
         const uint64_t* row = level(k) + p * I.bw;
         int w = from >> 6;
         if (w >= I.bw) return -1;
@@ -471,10 +539,18 @@ struct Searcher {
         }
     }
 
-    __device__ void emit(const Lm<W>& mv) {
-        const uint64_t h = (uint64_t)mv.h, lo = (uint64_t)mv.lo;
-        const unsigned long long at = atomicAdd(&ctr[inst].out_count, 1ull);
+    // Append the motifs of the lanes with ok (their keys) to the instance's
+    // output: one atomic per wave.
+    __device__ __forceinline__ void emit(const Lm<W>& mv, bool ok) {
+        const unsigned long long em = ballot(ok);
+        if (em == 0ull) return;
+        unsigned long long base = 0;
+        if (lane == __builtin_ctzll(em)) base = atomicAdd(&ctr[inst].out_count, (unsigned long long)__popcll(em));
+        base = __shfl(base, __builtin_ctzll(em), 64);
+        if (!ok) return;
+        const unsigned long long at = base + (unsigned long long)rank_below(em);
         if (at < (unsigned long long)I.out_cap) {
+            const uint64_t h = (uint64_t)mv.h, lo = (uint64_t)mv.lo;
             uint64_t* dst = keys + (I.out_off + (int64_t)at) * W;
             dst[0] = key_word<W>(h, lo, 0, I.l < 32 ? I.l : 32);
             if (W == 2) dst[1] = I.l > 32 ? key_word<W>(h, lo, 32, I.l) : 0ull;
@@ -483,282 +559,599 @@ struct Searcher {
         }
     }
 
-    // Check candidates cand[0..nc) against every remaining string of level k
-    // (Algorithm 2's isMotif on the filtered rows).
-    //
-    // Staged survivors: one string segment at a time, fewest survivors first,
-    // over the candidates still alive.  With A alive candidates padded to a
-    // power of two Ap, lane (sub, c) tests candidate c against survivors
-    // sub, sub + 64/Ap, ... of the segment; a wave ballot folded over the
-    // replicas gives which candidates have a survivor within d.  Those are
-    // compacted to the front of cand and the rest are dropped, so a segment
-    // costs ceil(size * Ap / 64) steps.  Unstaged (too many survivors for
-    // LDS): lane c checks candidate c against the level bitsets.
-    __device__ void verify(int k, int nc, bool staged) {
-        const int d = I.d;
-        if (staged) {
-            int A = nc;
-            const int R = S.nseg;
-            for (int g = 0; g < R && A > 0; g++) {
-                const int a = S.voff[g], e = S.voff[g + 1];
-                const int lg = A > 32 ? 6 : A > 16 ? 5 : A > 8 ? 4 : A > 4 ? 3 : A > 2 ? 2 : A > 1 ? 1 : 0;
-                const int Ap = 1 << lg, P = 64 >> lg;
-                const int ci = lane & (Ap - 1), sub = lane >> lg;
-                const bool vc = ci < A;
-                const Lm<W> mv = S.cand[vc ? ci : 0];
-                bool hit = false;
-                if (vc)
-                    for (int q = a + sub; q < e; q += P) hit |= pc(dmask(mv, S.vset[q])) <= d;
-                uint64_t m = ballot(hit);
-                for (int sh = 32; sh >= Ap; sh >>= 1) m |= m >> sh;
-                const uint64_t found = m & (A >= 64 ? ~0ull : ((1ull << A) - 1ull));
-                const bool keep = lane < A && ((found >> lane) & 1ull);
-                const Lm<W> mk = S.cand[lane < A ? lane : 0];
-                __syncthreads();
-                if (keep) S.cand[rank_below(found)] = mk;
-                __syncthreads();
-                A = __popcll(found);
-            }
-            if (lane < A) emit(S.cand[lane]);
-            __syncthreads();
-            return;
+    // Staged l-mer i: 4-byte packed (planes in the low and high 16 bits)
+    // when l <= 16, else the plain l-mer.
+    __device__ __forceinline__ uint32_t* s2h() const { return reinterpret_cast<uint32_t*>(s2); }
+    __device__ __forceinline__ Lm<W> s2get(int i) const {
+        if (W == 1 && half) {
+            const uint32_t v = s2h()[i];
+            Lm<W> x;
+            x.h = (M)(v & 0xFFFFu);
+            x.lo = (M)(v >> 16);
+            return x;
         }
-        const Lm<W> mv = S.cand[lane < nc ? lane : 0];
-        bool ok = lane < nc;
-        const uint32_t rows = S.rows[k];
-        for (int j = 0; j < I.n; j++) {
-            if (!((rows >> j) & 1u)) continue;
-            if (ballot(ok) == 0ull) break;
-            bool found = false;
-            const uint64_t* row = level(k) + j * I.bw;
-            for (int w = 0; w < I.bw; w++) {
-                uint64_t bits = row[w];
-                while (bits) {
-                    const int b = __builtin_ctzll(bits);
-                    bits &= bits - 1;
-                    found |= pc(dmask(mv, L[j * I.r + w * 64 + b])) <= d;
-                }
-                if (ballot(ok && !found) == 0ull) break;
-            }
-            ok &= found;
-        }
-        if (ok) emit(mv);
+        return s2[i];
     }
 
-    // Stage the survivors of level k into LDS if they fit: one segment per
-    // remaining string, segments ordered by survivor count (ties: lower
-    // string first), so the check meets the most selective strings first.
-    __device__ bool stage(int k) {
+    // Segments of the strings in vrows at level k, fewest survivors first
+    // (ties: lower string first), and, if their survivors fit the staging
+    // area, the survivors themselves in that order.  Returns whether they
+    // were staged.
+    __device__ __forceinline__ bool stage_rows(int k, uint32_t vrows) {
         const int n = I.n;
-        const uint32_t rows = S.rows[k];
-        const bool mine = lane < n && ((rows >> lane) & 1u);
+        const bool mine = lane < n && ((vrows >> lane) & 1u);
         const int c = mine ? (int)cnt16(k, lane) : 0;
         const int incl = wave_incl_scan(c);
         const int tot = __shfl(incl, 63, 64);
-        if (tot > kVCap) return false;
-        // rank of this string among the remaining ones by (count, index)
         int rank = 0;
         for (int j = 0; j < n; j++) {
             const int cj = __shfl(c, j, 64);
-            const bool in = (rows >> j) & 1u;
+            const bool in = (vrows >> j) & 1u;
             rank += (in && (cj < c || (cj == c && j < lane))) ? 1 : 0;
         }
-        // segment starts: prefix sum of the counts in rank order
-        const unsigned long long inm = ballot(mine);
-        const int R = __popcll(inm);
-        if (mine) S.voff[rank] = (uint16_t)c;  // count, turned into a start below
+        const int R = __popcll(ballot(mine));
         __syncthreads();
-        const int cr = lane < R ? (int)S.voff[lane] : 0;
+        if (mine) {
+            S.segoff[rank] = (uint16_t)c;  // count, turned into a start below
+            S.segrow[rank] = (uint8_t)lane;
+        }
+        __syncthreads();
+        const int cr = lane < R ? (int)S.segoff[lane] : 0;
         const int ir = wave_incl_scan(cr);
         __syncthreads();
-        if (lane < R) S.voff[lane] = (uint16_t)(ir - cr);
+        if (lane < R) S.segoff[lane] = (uint16_t)(ir - cr);
         if (lane == 0) {
-            S.voff[R] = (uint16_t)tot;
+            S.segoff[R] = (uint16_t)(tot < 65535 ? tot : 65535);
             S.nseg = R;
         }
         __syncthreads();
-        if (mine) S.rowbase[lane] = S.voff[rank];
+        if (tot > scap || R == 0) return R == 0;
+        const int rowbase = mine ? (int)S.segoff[rank] : 0;
         const int natural = incl - c;  // start of this string in index order
-        __syncthreads();
-        // slot -> l-mer index first (ALU only), then one independent load per
-        // slot
         const uint64_t* lvk = level(k);
         const int total = n * I.bw;
         int done = 0;
         for (int i0 = 0; i0 < total; i0 += 64) {
             const int i = i0 + lane;
             const int j = row_of(i);
-            uint64_t bits = (i < total && ((rows >> j) & 1u)) ? lvk[i] : 0ull;
+            uint64_t bits = (i < total && ((vrows >> j) & 1u)) ? lvk[i] : 0ull;
             const int cb = pc(bits);
             const int inc = wave_incl_scan(cb);
-            const int nat_j = __shfl(natural, j < 64 ? j : 0, 64);
-            int o = (int)S.rowbase[j < kMaxN ? j : 0] + (done + inc - cb - nat_j);
+            const int jj = j < 64 ? j : 0;
+            const int nat_j = __shfl(natural, jj, 64);
+            const int base_j = __shfl(rowbase, jj, 64);
+            int o = base_j + (done + inc - cb - nat_j);
             const int w = i - j * I.bw;
             while (bits) {
                 const int b = __builtin_ctzll(bits);
                 bits &= bits - 1;
-                S.vset[o++].h = (M)(j * I.r + w * 64 + b);
+                const int g = j * I.r + w * 64 + b;
+                if (W == 1 && half) s2h()[o++] = (uint32_t)g;
+                else s2[o++].h = (M)g;
             }
             done += __shfl(inc, 63, 64);
         }
         __syncthreads();
-        for (int q = lane; q < tot; q += 64) S.vset[q] = L[(int)S.vset[q].h];
+        // four loads in flight per lane
+        for (int q0 = 0; q0 < tot; q0 += 256) {
+            Lm<W> x[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int q = q0 + 64 * u + lane;
+                if (q < tot) x[u] = L[(W == 1 && half) ? (int)s2h()[q] : (int)s2[q].h];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int q = q0 + 64 * u + lane;
+                if (q < tot) {
+                    if (W == 1 && half) s2h()[q] = (uint32_t)x[u].h | ((uint32_t)x[u].lo << 16);
+                    else s2[q] = x[u];
+                }
+            }
+        }
         __syncthreads();
         return true;
     }
 
-    // Algorithm 1 on the stack st[0..k) with budgets d, pruned by negative
-    // budgets, by the pair condition on suffixes (Hd > r_i + r_j) and by
-    // Theorem 1 on suffixes of every triple (Cd > r_i + r_j + r_q); a leaf is
-    // reported only with every budget >= 0.  Wave-parallel: each step pops up
-    // to 16 nodes from the top of the node stack and lanes evaluate their 4
-    // children; surviving internal children are pushed (ballot + prefix
-    // sum), complete l-mers go to the candidate buffer.  A node is its prefix
-    // (bit-planes of positions < depth) and its depth; the budgets are
-    // recomputed from the prefix.  The stack's top kRing entries live in an
-    // LDS ring; older entries move to this wave's global node area in blocks
-    // of 64 when the ring fills and come back when pops reach them.
-    __device__ void generate(int k) {
-        const bool staged = stage(k);
-        switch (k) {
-            case 1: gen_tree<1>(staged); break;
-            case 2: gen_tree<2>(staged); break;
-            case 3: if constexpr (TMAX >= 3) gen_tree<3>(staged); break;
-            case 4: if constexpr (TMAX >= 4) gen_tree<4>(staged); break;
-            case 5: if constexpr (TMAX >= 5) gen_tree<5>(staged); break;
-            case 6: if constexpr (TMAX >= 6) gen_tree<6>(staged); break;
-            case 7: if constexpr (TMAX >= 7) gen_tree<7>(staged); break;
-            case 8: if constexpr (TMAX >= 8) gen_tree<8>(staged); break;
-            default: break;
-        }
-    }
-
-    // The tree for a stack of exactly K members (K known at compile time,
-    // so every per-member test is unrolled and evaluated without branches).
-    template <int K>
-    __device__ void gen_tree(bool staged) {
-        const int k = K;
-        Lm<W> s[K];
-        M e[K][K];
-#pragma unroll
-        for (int a = 0; a < K; a++) {
-            s[a] = S.st[a];
-#pragma unroll
-            for (int b = 0; b < K; b++) e[a][b] = (a < b) ? S.E[a][b] : (M)0;
-        }
-        const int l = I.l, d = I.d;
-        if (lane == 0) {
-            S.rh[0] = 0;
-            S.rl[0] = 0;
-            S.rd[0] = 0;
+    // Windows of the survivors of string p at level k with rank in [a, b)
+    // (b - a <= kTailSlots) into S.xs; returns how many.
+    __device__ __forceinline__ int list_candidates(int k, int p, int a, int b) {
+        const uint64_t* row = level(k) + p * I.bw;
+        const uint64_t w = lane < I.bw ? row[lane] : 0ull;
+        const int c = pc(w);
+        const int incl = wave_incl_scan(c);
+        const int tot = __shfl(incl, 63, 64);
+        const int hi = b < tot ? b : tot;
+        int rank = incl - c;
+        uint64_t bits = w;
+        while (bits && rank < hi) {
+            const int bb = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            if (rank >= a) S.xs[rank - a] = lane * 64 + bb;
+            rank++;
         }
         __syncthreads();
-        int size = 1;  // stack entries
-        int g = 0;     // entries [0, g) are in the global node area, [g, size) in the ring
-        int nc = 0;    // candidates waiting in S.cand
-        while (size > 0) {
-            if (size > kNodeCap - 4 * kNodeBatch) {
-                // cannot happen (each depth holds at most one batch of 4*16
-                // children); kept as a guard so the stack never overruns
+        return hi > a ? hi - a : 0;
+    }
+
+    // Survivor bits of slot s: staged l-mer v is kept iff Hd(cand, v) <= 2d
+    // and, with the Theorem 1 filter, Cd(s_a, cand, v) <= 3d for every stack
+    // member s_a (a < k).  Returns whether every segment keeps a survivor.
+    __device__ __forceinline__ bool filter_slot(int k, int s, int tot) {
+        const Lm<W> cand = ut[s];
+        const int d2 = 2 * I.d, thr3 = 3 * I.d;
+        Lm<W> sa[TMAX];
+        M ea[TMAX];
+        int ha[TMAX];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            const int aa = a < k ? a : 0;
+            sa[a] = S.st[aa];
+            ea[a] = dmask(sa[a], cand);
+            ha[a] = pc(ea[a]);
+        }
+        for (int i0 = 0; i0 < tot; i0 += 256) {
+            Lm<W> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = i0 + 64 * u + lane;
+                v[u] = s2get(i < tot ? i : 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = i0 + 64 * u + lane;
+                bool keep = false;
+                if (i < tot) {
+                    const int hv = pc(dmask(cand, v[u]));
+                    keep = hv <= d2;
+                    if (I.triple) {
+#pragma unroll
+                        for (int a = 0; a < TMAX; a++) {
+                            if (a < k) {
+                                const M da = dmask(sa[a], v[u]);
+                                keep &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
+                            }
+                        }
+                    }
+                }
+                const unsigned long long bm = ballot(keep);
+                if (lane == 0 && i0 + 64 * u < tot) memb[s * mw + ((i0 >> 6) + u)] = bm;
+            }
+        }
+        __syncthreads();
+        // every segment keeps at least one survivor
+        bool empty = false;
+        if (lane < S.nseg) {
+            const int a = S.segoff[lane], b = S.segoff[lane + 1];
+            uint64_t acc = 0;
+            for (int w = a >> 6; w <= (b - 1) >> 6; w++) {
+                const int lo = a - 64 * w, hi = b - 64 * w;
+                uint64_t m = ~0ull;
+                if (lo > 0) m &= ~0ull << lo;
+                if (hi < 64) m &= (1ull << hi) - 1ull;
+                acc |= memb[s * mw + w] & m;
+            }
+            empty = acc == 0ull;
+        }
+        return ballot(empty) == 0ull;
+    }
+
+    // ---- the tail batch: generation over subtrees, check, emission ----
+
+    // Valid children (4-bit mask) of the node at depth P whose prefix is mv
+    // (characters 0..P-1), for members mh/ml[0..K) with pair masks e2:
+    // Algorithm 1's prune with budgets d - Hd(prefix) and suffixes from P+1.
+    __device__ __forceinline__ uint32_t expand(const M (&mh)[TMAX], const M (&ml)[TMAX],
+                                               const M (&e2)[TMAX][TMAX], int K, M vh, M vl,
+                                               int P) const {
+        const M below = low_bits((M)0, P);
+        const int d = I.d;
+        int rb[TMAX];
+        uint32_t oh[TMAX];
+        uint32_t allowed = 0xFu;
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            if (a < K) {
+                rb[a] = d - pc((M)(((vh ^ mh[a]) | (vl ^ ml[a])) & below));
+                const uint32_t ca = (uint32_t)((((uint64_t)mh[a] >> P) & 1ull) << 1 |
+                                               (((uint64_t)ml[a] >> P) & 1ull));
+                oh[a] = 1u << ca;
+                allowed &= rb[a] >= 1 ? 0xFu : rb[a] == 0 ? oh[a] : 0u;
+            } else {
+                rb[a] = 0;
+                oh[a] = 0xFu;
+            }
+        }
+        const int sfx = P + 1;
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+#pragma unroll
+            for (int b = a + 1; b < TMAX; b++)
+                if (b < K) allowed &= slack2(rb[a] + rb[b] - pc(suf(e2[a][b], sfx)), oh[a], oh[b]);
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+#pragma unroll
+            for (int b = a + 1; b < TMAX; b++)
+#pragma unroll
+                for (int c = b + 1; c < TMAX; c++)
+                    if (c < K) {
+                        const M u = (M)(e2[a][b] | e2[a][c]);
+                        const M x = (M)(e2[a][b] & e2[a][c] & e2[b][c]);
+                        const int cd = pc(suf(u, sfx)) + pc(suf(x, sfx));
+                        allowed &= slack3(rb[a] + rb[b] + rb[c] - cd, oh[a], oh[b], oh[c]);
+                    }
+        return allowed;
+    }
+
+    // Whether the node at depth P with prefix mv is in the pruned tree
+    // (budgets >= 0, pair and triple conditions on suffixes from P).  A
+    // valid node's ancestors are valid too (each condition only loosens
+    // towards the root), so the valid nodes of one depth split the tree's
+    // leaves into disjoint subtrees.
+    __device__ __forceinline__ bool node_valid(const M (&mh)[TMAX], const M (&ml)[TMAX],
+                                               const M (&e2)[TMAX][TMAX], int K, M vh, M vl,
+                                               int P) const {
+        const M below = low_bits((M)0, P);
+        int rb[TMAX];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            rb[a] = a < K ? I.d - pc((M)(((vh ^ mh[a]) | (vl ^ ml[a])) & below)) : 0;
+            ok &= rb[a] >= 0;
+        }
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+#pragma unroll
+            for (int b = a + 1; b < TMAX; b++)
+                if (b < K) ok &= pc(suf(e2[a][b], P)) <= rb[a] + rb[b];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+#pragma unroll
+            for (int b = a + 1; b < TMAX; b++)
+#pragma unroll
+                for (int c = b + 1; c < TMAX; c++)
+                    if (c < K) {
+                        const M u = (M)(e2[a][b] | e2[a][c]);
+                        const M x = (M)(e2[a][b] & e2[a][c] & e2[b][c]);
+                        ok &= pc(suf(u, P)) + pc(suf(x, P)) <= rb[a] + rb[b] + rb[c];
+                    }
+        return ok;
+    }
+
+    // Check the buffered l-mers against every remaining string, one string
+    // (segment) at a time, fewest survivors first: lanes take one l-mer each
+    // and look for a survivor of that string within d (the l-mer's slot's
+    // survivor bits over the staged segment, or the string's level-k bitset
+    // when nothing is staged); the l-mers that found one are compacted in
+    // place and go on to the next string.  The rest are motifs.
+    __device__ __forceinline__ void check_leaves(int k, int nl, bool staged) {
+        const int nseg = S.nseg, d = I.d, bw = I.bw, r = I.r;
+        const uint64_t* lvk = k >= 2 ? level(k) : nullptr;
+        for (int g = 0; g < nseg && nl > 0; g++) {
+            int a = 0, b = 0, row = 0;
+            if (staged) {
+                a = S.segoff[g];
+                b = S.segoff[g + 1];
+            } else {
+                row = S.segrow[g];
+            }
+            int keep_n = 0;
+            for (int c0 = 0; c0 < nl; c0 += 64) {
+                const int i = c0 + lane;
+                const bool act = i < nl;
+                Lm<W> mv;
+                mv.h = 0;
+                mv.lo = 0;
+                int sl = 0;
+                if (act) {
+                    mv = leaf[i];
+                    sl = leafslot[i];
+                }
+                bool hit = false;
+                if (act) {
+                    // up to four candidates' loads in flight per round
+                    if (staged) {
+                        for (int w = a >> 6; w <= (b - 1) >> 6 && !hit; w++) {
+                            uint64_t m = ~0ull;
+                            if (a - 64 * w > 0) m &= ~0ull << (a - 64 * w);
+                            if (b - 64 * w < 64) m &= (1ull << (b - 64 * w)) - 1ull;
+                            uint64_t bits = memb[sl * mw + w] & m;
+                            while (bits && !hit) {
+                                Lm<W> v[4];
+                                bool use[4];
+#pragma unroll
+                                for (int u = 0; u < 4; u++) {
+                                    use[u] = bits != 0ull;
+                                    const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : a;
+                                    bits &= bits - 1;
+                                    v[u] = s2get(x);
+                                }
+#pragma unroll
+                                for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
+                            }
+                        }
+                    } else {
+                        for (int w = 0; w < bw && !hit; w++) {
+                            uint64_t bits = lvk[row * bw + w];
+                            while (bits && !hit) {
+                                Lm<W> v[4];
+                                bool use[4];
+#pragma unroll
+                                for (int u = 0; u < 4; u++) {
+                                    use[u] = bits != 0ull;
+                                    const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : 0;
+                                    bits &= bits - 1;
+                                    v[u] = L[row * r + x];
+                                }
+#pragma unroll
+                                for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
+                            }
+                        }
+                    }
+                }
+                const unsigned long long hm = ballot(hit);
+                __syncthreads();  // every lane has read its l-mer before the compaction
+                if (hit) {
+                    const int at = keep_n + rank_below(hm);
+                    leaf[at] = mv;
+                    leafslot[at] = (uint8_t)sl;
+                }
+                keep_n += __popcll(hm);
+                __syncthreads();
+            }
+            nl = keep_n;
+        }
+        for (int c0 = 0; c0 < nl; c0 += 64) {
+            const int i = c0 + lane;
+            Lm<W> mv;
+            mv.h = 0;
+            mv.lo = 0;
+            const bool ok = i < nl;
+            if (ok) mv = leaf[i];
+            emit(mv, ok);
+        }
+        __syncthreads();
+    }
+
+    // Member K-1 is the slot's candidate (compile-time indices only: K is
+    // uniform but not a constant).
+    __device__ __forceinline__ void load_slot(M (&mh)[TMAX], M (&ml)[TMAX], M (&e2)[TMAX][TMAX],
+                                              int K, int sl) const {
+        const Lm<W> c = ut[sl];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+            if (a == K - 1) {
+                mh[a] = (M)c.h;
+                ml[a] = (M)c.lo;
+            }
+#pragma unroll
+        for (int a = 0; a < TMAX; a++)
+#pragma unroll
+            for (int b = a + 1; b < TMAX; b++)
+                if (b == K - 1) e2[a][b] = (M)((mh[a] ^ (M)c.h) | (ml[a] ^ (M)c.lo));
+    }
+
+    // Start a walk at the valid node (vh, vl) of depth P: its child nibble,
+    // or a leaf when P == l (returned).
+    __device__ __forceinline__ bool start(const M (&mh)[TMAX], const M (&ml)[TMAX],
+                                          const M (&e2)[TMAX][TMAX], int K, M vh, M vl, int P,
+                                          uint64_t (&av)[NW], uint64_t& nz, bool& has) const {
+#pragma unroll
+        for (int i = 0; i < NW; i++) av[i] = 0ull;
+        nz = 0;
+        if (P == I.l) return true;
+        const uint32_t nb = expand(mh, ml, e2, K, vh, vl, P);
+        if (nb) {
+#pragma unroll
+            for (int i = 0; i < NW; i++)
+                if (i == (P >> 4)) av[i] = (uint64_t)nb << (4 * (P & 15));
+            nz = 1ull << P;
+            has = true;
+        }
+        return false;
+    }
+
+    // Generate the common d-neighbourhoods of the live slots' stacks
+    // (shared members st[0..K-2], last member ut[slot]) and check them.
+    // Lanes walk subtrees on their own; the first subtrees are the valid
+    // nodes at depth D of every live slot's tree, and when those are handed
+    // out, idle lanes take the shallowest pending child of a busy lane
+    // (which drops it from its own walk), so every node is visited once.
+    __device__ __forceinline__ void tail_generate(int k, int K, uint32_t alive, bool staged) {
+        const int l = I.l;
+        const int nalive = __popc(alive);
+        if (nalive == 0) return;
+        if (lane == 0) {
+            int q = 0;
+            for (int s = 0; s < kTailSlots; s++)
+                if ((alive >> s) & 1u) S.aslot[q++] = s;
+        }
+        __syncthreads();
+        // shared members and their pair masks (uniform)
+        M mh[TMAX], ml[TMAX], e2[TMAX][TMAX];
+#pragma unroll
+        for (int a = 0; a < TMAX; a++) {
+            const int aa = a < K - 1 ? a : 0;
+            mh[a] = (M)S.st[aa].h;
+            ml[a] = (M)S.st[aa].lo;
+#pragma unroll
+            for (int b = 0; b < TMAX; b++) e2[a][b] = (a < b && b < K - 1) ? (M)S.E[a][b] : (M)0;
+        }
+        int D = nalive >= 4 ? 2 : 3;
+        if (D > l) D = l;
+        const int units = nalive << (2 * D);
+        int next = 0;
+        int nl = 0;
+        bool has = false;
+        int slot = 0;
+        M vh = 0, vl = 0;
+        uint64_t av[NW];
+#pragma unroll
+        for (int i = 0; i < NW; i++) av[i] = 0ull;
+        uint64_t nz = 0;  // depths whose nibble is not zero
+        long long guard = 0;
+        for (;;) {
+            if (++guard > kStepLimit) {
                 if (lane == 0) atomicOr(&ctr[inst].flags, kFlagNodeOverflow);
                 break;
             }
-            const int B = size < kNodeBatch ? size : kNodeBatch;
-            const int base = size - B;
-            if (base < g) {
-                // bring back the block of 64 below the ring (the ring then
-                // holds fewer than 16 + 64 entries, so no slot is live twice)
-                g -= 64;
-                const Node x = nodes[g + lane];
-                const int sl = (g + lane) & (kRing - 1);
-                S.rh[sl] = (M)x.h;
-                S.rl[sl] = (M)x.lo;
-                S.rd[sl] = (uint8_t)x.depth;
-                __syncthreads();
-            }
-            const int ni = lane >> 2;
-            const int alpha = lane & 3;
-            const bool active = ni < B;
-            const int rs = (base + (active ? ni : 0)) & (kRing - 1);
-            const M nh = S.rh[rs];
-            const M nl = S.rl[rs];
-            const int p = (int)S.rd[rs];
-            __syncthreads();  // every lane has read its node before pushes overwrite
-            size = base;
-            const M below = p >= 8 * (int)sizeof(M) ? ~(M)0 : (((M)1 << p) - (M)1);
-            const int sfx = p + 1;
-            bool valid = active;
-            int rb[K];
-#pragma unroll
-            for (int a = 0; a < K; a++) {
-                const M da = ((nh ^ s[a].h) | (nl ^ s[a].lo)) & below;
-                const int ca = (int)((((uint64_t)s[a].h >> p) & 1ull) << 1 | (((uint64_t)s[a].lo >> p) & 1ull));
-                rb[a] = d - pc(da) - (ca != alpha ? 1 : 0);
-                valid &= rb[a] >= 0;
-            }
-#pragma unroll
-            for (int a = 0; a < K; a++)
-#pragma unroll
-                for (int b = a + 1; b < K; b++) valid &= pc(suf(e[a][b], sfx)) <= rb[a] + rb[b];
-#pragma unroll
-            for (int a = 0; a < K; a++)
-#pragma unroll
-                for (int b = a + 1; b < K; b++)
-#pragma unroll
-                    for (int c = b + 1; c < K; c++) {
-                        const M u = suf((M)(e[a][b] | e[a][c]), sfx);
-                        const M x = suf((M)(e[a][b] & e[a][c] & e[b][c]), sfx);
-                        valid &= pc(u) + pc(x) <= rb[a] + rb[b] + rb[c];
+            bool isleaf = false;
+            const unsigned long long need = ballot(!has);
+            const int nidle = __popcll(need);
+            if (next < units) {
+                // hand out the depth-D subtrees (batched: at least 8 idle lanes)
+                if (nidle >= 8 || need == ~0ull) {
+                    if (!has) {
+                        const int u = next + rank_below(need);
+                        if (u < units) {
+                            slot = S.aslot[u >> (2 * D)];
+                            load_slot(mh, ml, e2, K, slot);
+                            const int pre = u & ((1 << (2 * D)) - 1);
+                            vh = 0;
+                            vl = 0;
+                            for (int q = 0; q < D; q++) {
+                                const int ch = (pre >> (2 * (D - 1 - q))) & 3;
+                                vh |= (M)(ch >> 1) << q;
+                                vl |= (M)(ch & 1) << q;
+                            }
+                            if (node_valid(mh, ml, e2, K, vh, vl, D))
+                                isleaf = start(mh, ml, e2, K, vh, vl, D, av, nz, has);
+                        }
                     }
-            const M ch = nh | ((M)(alpha >> 1) << p);
-            const M cl = nl | ((M)(alpha & 1) << p);
-            const bool leaf = valid && sfx == l;
-            const bool push = valid && sfx < l;
-            const unsigned long long pm = ballot(push);
-            const int npush = __popcll(pm);
-            if (size + npush - g > kRing) {
-                // move the oldest 64 ring entries to the global node area
-                // (the ring holds more than kRing - 64 >= 64 of them)
-                const int sl = (g + lane) & (kRing - 1);
-                Node x;
-                x.h = (uint64_t)S.rh[sl];
-                x.lo = (uint64_t)S.rl[sl];
-                x.bud = 0;
-                x.depth = (uint32_t)S.rd[sl];
-                x.pad = 0;
-                nodes[g + lane] = x;
-                g += 64;
-                __syncthreads();  // spilled slots read before the pushes reuse them
+                    next += nidle;
+                }
+            } else if (nidle >= 4) {
+                // donation: busy lanes with two or more pending children give
+                // away the shallowest one
+                int q0 = 0;
+                uint32_t nib0 = 0;
+                bool donor = false;
+                if (has) {
+                    q0 = __builtin_ctzll(nz);
+#pragma unroll
+                    for (int i = 0; i < NW; i++)
+                        if (i == (q0 >> 4)) nib0 = (uint32_t)(av[i] >> (4 * (q0 & 15))) & 0xFu;
+                    donor = __popcll(nz) >= 2 || __popc(nib0) >= 2;
+                }
+                const unsigned long long dm = ballot(donor);
+                const int ndon = __popcll(dm) < nidle ? __popcll(dm) : nidle;
+                if (ndon > 0) {
+                    if (donor && rank_below(dm) < ndon) {
+                        const int ch = __builtin_ctz(nib0);
+                        nib0 &= nib0 - 1;
+#pragma unroll
+                        for (int i = 0; i < NW; i++)
+                            if (i == (q0 >> 4)) {
+                                const int sh = 4 * (q0 & 15);
+                                av[i] = (av[i] & ~(0xFull << sh)) | ((uint64_t)nib0 << sh);
+                            }
+                        if (!nib0) nz &= ~(1ull << q0);
+                        const M keep = low_bits((M)0, q0);
+                        const int at = rank_below(dm);
+                        S.dq_h[at] = (M)((vh & keep) | ((M)(ch >> 1) << q0));
+                        S.dq_l[at] = (M)((vl & keep) | ((M)(ch & 1) << q0));
+                        S.dq_d[at] = (uint8_t)(q0 + 1);
+                        S.dq_s[at] = (uint8_t)slot;
+                    }
+                    __syncthreads();
+                    if (!has && rank_below(need) < ndon) {
+                        const int at = rank_below(need);
+                        slot = S.dq_s[at];
+                        load_slot(mh, ml, e2, K, slot);
+                        vh = S.dq_h[at];
+                        vl = S.dq_l[at];
+                        isleaf = start(mh, ml, e2, K, vh, vl, (int)S.dq_d[at], av, nz, has);
+                    }
+                    __syncthreads();
+                }
             }
-            if (push) {
-                const int sl = (size + rank_below(pm)) & (kRing - 1);
-                S.rh[sl] = ch;
-                S.rl[sl] = cl;
-                S.rd[sl] = (uint8_t)sfx;
+            if (has && !isleaf) {
+                // deepest depth with an unvisited child
+                const int q = 63 - __builtin_clzll(nz);
+                const int wq = q >> 4, sh = 4 * (q & 15);
+                uint32_t nib = 0;
+#pragma unroll
+                for (int i = 0; i < NW; i++)
+                    if (i == wq) nib = (uint32_t)(av[i] >> sh) & 0xFu;
+                const int ch = __builtin_ctz(nib);
+                nib &= nib - 1;
+#pragma unroll
+                for (int i = 0; i < NW; i++)
+                    if (i == wq) av[i] = (av[i] & ~(0xFull << sh)) | ((uint64_t)nib << sh);
+                if (!nib) nz &= ~(1ull << q);
+                const M keep = low_bits((M)0, q);
+                vh = (M)((vh & keep) | ((M)(ch >> 1) << q));
+                vl = (M)((vl & keep) | ((M)(ch & 1) << q));
+                if (q + 1 == l) {
+                    isleaf = true;
+                } else {
+                    const uint32_t nb = expand(mh, ml, e2, K, vh, vl, q + 1);
+                    if (nb) {
+                        const int w1 = (q + 1) >> 4, s1 = 4 * ((q + 1) & 15);
+#pragma unroll
+                        for (int i = 0; i < NW; i++)
+                            if (i == w1) av[i] |= (uint64_t)nb << s1;
+                        nz |= 1ull << (q + 1);
+                    }
+                }
+                if (nz == 0ull) has = false;
             }
-            size += npush;
-            const unsigned long long lm = ballot(leaf);
-            if (leaf) {
-                Lm<W> mv;
-                mv.h = ch;
-                mv.lo = cl;
-                S.cand[nc + rank_below(lm)] = mv;
+            const unsigned long long lm = ballot(isleaf);
+            if (isleaf) {
+                const int at = nl + rank_below(lm);
+                leaf[at].h = vh;
+                leaf[at].lo = vl;
+                leafslot[at] = (uint8_t)slot;
             }
-            nc += __popcll(lm);
-            __syncthreads();
-            if (nc >= 64) {
-                verify(k, 64, staged);
+            nl += __popcll(lm);
+            const bool done = ballot(has) == 0ull && next >= units;
+            if (nl > kLeafCap - 64 || (done && nl > 0)) {
                 __syncthreads();
-                const int rest = nc - 64;
-                Lm<W> mv = S.cand[64 + (lane < rest ? lane : 0)];
-                __syncthreads();
-                if (lane < rest) S.cand[lane] = mv;
-                nc = rest;
-                __syncthreads();
+                check_leaves(k, nl, staged);
+                nl = 0;
             }
+            if (done) break;
         }
-        if (nc > 0) verify(k, nc, staged);
         __syncthreads();
+    }
+
+    // Tail batch.  p >= 0: the stack st[0..k) is followed by each survivor
+    // of string p at level k with rank in [ra, rb).  p < 0: the stack
+    // st[0..k) is complete (one slot).
+    __device__ __forceinline__ void tail(int k, int p, int ra, int rb) {
+        const uint32_t vrows = p >= 0 ? (S.rows[k] & ~(1u << p)) : S.rows[k];
+        const bool staged = stage_rows(k, vrows);
+        const int tot = S.segoff[S.nseg];
+        if (p < 0) {
+            if (lane == 0) ut[0] = S.st[k - 1];
+            if (staged)
+                for (int w = lane; w < mw; w += 64) {
+                    const int hi = tot - 64 * w;
+                    memb[w] = hi >= 64 ? ~0ull : hi > 0 ? (1ull << hi) - 1ull : 0ull;
+                }
+            __syncthreads();
+            ra = 0;
+            rb = 1;
+        }
+        for (int a = ra; a < rb; a += kTailSlots) {
+            const int b = rb - a > kTailSlots ? a + kTailSlots : rb;
+            int T = 1;
+            uint32_t alive = 1u;
+            if (p >= 0) {
+                T = list_candidates(k, p, a, b);
+                if (T <= 0) break;
+                if (lane < T) ut[lane] = L[p * I.r + S.xs[lane]];
+                __syncthreads();
+                alive = 0;
+                for (int s = 0; s < T; s++) {
+                    const bool ok = (!staged || S.nseg == 0) ? true : filter_slot(k, s, tot);
+                    if (ok) alive |= 1u << s;
+                }
+                if (staged && S.nseg > 0) __syncthreads();
+            }
+            tail_generate(k, p >= 0 ? k + 1 : k, alive, staged);
+            if (T < b - a) break;
+        }
     }
 };
 
@@ -775,18 +1168,23 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                                                const uint64_t* __restrict__ items,
                                                uint64_t* __restrict__ parts,
                                                QueueCounters* __restrict__ qs,
-                                               Node* __restrict__ node_scratch,
                                                uint64_t* __restrict__ keys,
                                                InstCounters* __restrict__ ctr,
-                                               int level_words, int phase, int split) {
+                                               int level_words, int lv_words, int s2cap,
+                                               int phase, int split) {
     extern __shared__ uint64_t dyn[];
     __shared__ SearchLds<W, TMAX> S;
     __shared__ unsigned cntw[(TMAX + 1) * kMaxN];
     const int lane = lane_id();
-    Node* nodes = node_scratch + (int64_t)blockIdx.x * kNodeCap;
     QueueCounters* q = qs + phase;
     QueueCounters* qp = qs + 1;
     const uint64_t* src = phase == 0 ? items : parts;
+    const int mw = (W == 1 ? 2 : 1) * s2cap / 64;  // survivor-bit words per slot
+    Lm<W>* s2 = reinterpret_cast<Lm<W>*>(dyn + lv_words);
+    uint64_t* memb = reinterpret_cast<uint64_t*>(s2 + s2cap);
+    Lm<W>* ut = reinterpret_cast<Lm<W>*>(memb + kTailSlots * mw);
+    Lm<W>* leaf = ut + kTailSlots;
+    uint8_t* leafslot = reinterpret_cast<uint8_t*>(leaf + kLeafCap);
     for (;;) {
         if (lane == 0) {
             unsigned long long it = atomicAdd(&q->item_next, 1ull);
@@ -805,56 +1203,67 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         const int x2 = uni((int)(item & 0x7FF));
         const InstDev I = insts[inst];
         Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
-                             compat + I.compat_off, (uint64_t)u1, nodes, keys, ctr, lane};
-        sr.cntw = cntw;
-        sr.inv_bw = (65536 + I.bw - 1) / (I.bw > 0 ? I.bw : 1);
+                             compat + I.compat_off, (uint64_t)u1, keys, ctr, lane, cntw,
+                             (65536 + I.bw - 1) / (I.bw > 0 ? I.bw : 1),
+                             s2, memb, ut, leaf, leafslot, s2cap, mw, W == 1 && I.l <= 16,
+                             (W == 1 && I.l <= 16) ? 2 * s2cap : s2cap};
         if (lane == 0) {
             S.st[0] = sr.L[u1];
             S.rows[1] = (I.n >= 32 ? 0xFFFFFFFFu : ((1u << I.n) - 1u)) & ~1u;
         }
         __syncthreads();
         const int t = I.t < TMAX ? I.t : TMAX;
+        int k = 2;
         if (p2 == 0) {  // n == 1: the stack {u1} is complete, nothing to check
             if (lane == 0) S.rows[1] = 0;
             __syncthreads();
-            sr.generate(1);
+            k = 1;
+        } else if (!sr.push_filter(1, p2, x2)) {
             continue;
         }
-        if (!sr.push_filter(1, p2, x2)) continue;
-        int k = 2;
         bool descend = true;
         int rank2 = 0, rank2_end = 0x7FFFFFFF;  // survivor ranks this item covers at k == 2
         for (;;) {
             if (descend) {
+                int tp = -2, ra = 0, rb = 0;  // tail batch: string (-1: complete stack), ranks
+                int p = 0, cur = 0;
                 if (k >= t || S.rows[k] == 0u) {
-                    sr.generate(k);
+                    tp = -1;
+                } else {
+                    p = uni(sr.choose_row(k));
+                    if (k == 2) {
+                        const int c = uni((int)sr.cnt16(2, p));
+                        if (phase == 0) {
+                            if (c > split) {
+                                const int extra = (c - 1) / split;
+                                unsigned long long base = 0;
+                                if (lane == 0) base = atomicAdd(&qp->item_count, (unsigned long long)extra);
+                                base = __shfl(base, 0, 64);
+                                if (base + (unsigned long long)extra <= qp->item_cap) {
+                                    for (int e = lane; e < extra; e += 64)
+                                        parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
+                                    rank2_end = split;
+                                }
+                            }
+                        } else {
+                            rank2 = lo;
+                            rank2_end = lo + split;
+                            cur = uni(sr.nth_bit(2, p, lo));
+                            if (cur < 0) cur = 64 * I.bw;
+                        }
+                    }
+                    if (k == t - 1) {  // the last member: string p's survivors
+                        tp = p;
+                        ra = k == 2 ? rank2 : 0;
+                        rb = k == 2 ? rank2_end : 0x7FFFFFFF;
+                    }
+                }
+                if (tp != -2) {
+                    sr.tail(k, tp, ra, rb);
                     k--;
                     if (k < 2) break;
                     descend = false;
                     continue;
-                }
-                const int p = uni(sr.choose_row(k));
-                int cur = 0;
-                if (k == 2) {
-                    const int c = uni((int)sr.cnt16(2, p));
-                    if (phase == 0) {
-                        if (c > split) {
-                            const int extra = (c - 1) / split;
-                            unsigned long long base = 0;
-                            if (lane == 0) base = atomicAdd(&qp->item_count, (unsigned long long)extra);
-                            base = __shfl(base, 0, 64);
-                            if (base + (unsigned long long)extra <= qp->item_cap) {
-                                for (int e = lane; e < extra; e += 64)
-                                    parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
-                                rank2_end = split;
-                            }
-                        }
-                    } else {
-                        rank2 = lo;
-                        rank2_end = lo + split;
-                        cur = uni(sr.nth_bit(2, p, lo));
-                        if (cur < 0) cur = 64 * I.bw;
-                    }
                 }
                 if (lane == 0) {
                     S.prow[k] = p;
@@ -932,12 +1341,12 @@ __device__ __forceinline__ void bitonic_steps(A a, int P) {
 template <int KW> struct LdsKeys {
     Key<KW>* p;
     __device__ Key<KW> get(int i) const { return p[i]; }
-    __device__ void put(int i, const Key<KW>& v) const { p[i] = v; }
+    __device__ __forceinline__ void put(int i, const Key<KW>& v) const { p[i] = v; }
 };
 template <int KW> struct HbmKeys {
     Key<KW>* p;
     __device__ Key<KW> get(int i) const { return p[i]; }
-    __device__ void put(int i, const Key<KW>& v) const { p[i] = v; }
+    __device__ __forceinline__ void put(int i, const Key<KW>& v) const { p[i] = v; }
 };
 
 // Keep a[i] when i == 0 or a[i] != a[i-1]; compacted into g (block prefix sum).
@@ -1064,17 +1473,24 @@ hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
 }
 
 size_t search_lds_bytes(const LaunchPlan& p) {
-    int tm = p.tmax;
-    return (size_t)(tm > 1 ? tm - 1 : 1) * (size_t)p.level_words * 8u;
+    const size_t lm = p.words == 1 ? sizeof(Lm<1>) : sizeof(Lm<2>);
+    // levels 2 .. max(2, t-1): the last member never gets a level of its own
+    // (the tail batch replaces that push)
+    const size_t lv = (size_t)(p.tmax > 3 ? p.tmax - 2 : 1) * (size_t)p.level_words * 8u;
+    const size_t mw = (size_t)(p.words == 1 ? 2 : 1) * (size_t)(p.s2cap / 64);
+    const size_t tail = (size_t)p.s2cap * lm + (size_t)kTailSlots * mw * 8u +
+                        (size_t)kTailSlots * lm + (size_t)kLeafCap * lm + (size_t)kLeafCap;
+    return lv + tail;
 }
 
 template <int W, int TMAX>
 static hipError_t search_t(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
     const size_t lds = search_lds_bytes(p);
+    const int lv_words = (p.tmax > 3 ? p.tmax - 2 : 1) * p.level_words;
     for (int phase = 0; phase < 2; phase++) {
         hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
-                           (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.q, b.nodes, b.keys,
-                           b.ctr, p.level_words, phase, p.split);
+                           (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.q, b.keys, b.ctr,
+                           p.level_words, lv_words, p.s2cap, phase, p.split);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -2,8 +2,7 @@
 //
 // The same device pipeline as pms_solve_batch on one instance, with every
 // intermediate buffer (instance descriptor, character table, packed l-mers,
-// compat bit-matrix, work and part queues, generator node areas, emitted
-// keys, counters) carved out of `scratch`, a fixed device array of this
+// compat bit-matrix, work and part queues, emitted keys, counters) carved out of `scratch`, a fixed device array of this
 // library that each GPU holds until the process ends.  Inputs and outputs
 // are the caller's device buffers; the host side only validates sizes and
 // enqueues kernels on the caller's stream (no hipMalloc, no hipFree, no
@@ -21,7 +20,7 @@
 namespace pms {
 
 constexpr size_t kScratchBytes = size_t(256) << 20;  // PMS_NOALLOC_SCRATCH_BYTES
-constexpr int kNoallocWavesPerCu = 2;                  // persistent search waves per CU
+constexpr int kNoallocWavesPerCu = 20;                 // persistent search waves per CU
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -139,7 +138,6 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     const size_t o_compat = take((size_t)N * n * bw * 8);
     const size_t o_items = take((size_t)items * 8);
     const size_t o_parts = take((size_t)parts * 8);
-    const size_t o_nodes = take((size_t)blocks * kNodeCap * sizeof(Node));
     const size_t o_ctr = take(sizeof(InstCounters));
     const size_t o_q = take(2 * sizeof(QueueCounters));
     if (off >= kScratchBytes) return PMS_E_NOMEM;
@@ -158,7 +156,6 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     b.compat = (uint64_t*)(s + o_compat);
     b.items = (uint64_t*)(s + o_items);
     b.parts = (uint64_t*)(s + o_parts);
-    b.nodes = (Node*)(s + o_nodes);
     b.keys = (uint64_t*)(s + o_keys);
     b.ctr = (InstCounters*)(s + o_ctr);
     b.q = (QueueCounters*)(s + o_q);
@@ -191,6 +188,12 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     p.search_blocks = blocks;
     p.compat_kernel = 1;
     p.split = kSplitDefault;
+    p.s2cap = 1024;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return PMS_E_DEVICE;
+    while (p.s2cap > kStageCapMin && search_lds_bytes(p) > (size_t)lds_max) p.s2cap /= 2;
+    if (search_lds_bytes(p) > (size_t)lds_max) return PMS_E_UNSUPPORTED;
 
     uint32_t alpha4 = 0;
     for (int k = 0; k < 4; k++) alpha4 |= (uint32_t)(uint8_t)a[k] << (8 * k);

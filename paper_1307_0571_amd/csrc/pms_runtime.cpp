@@ -47,6 +47,19 @@ int device_cus() {
     return c;
 }
 
+int device_lds_per_block() {
+    static std::atomic<int> lds{0};
+    int v = lds.load();
+    if (v > 0) return v;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+        return 65536;
+    lds.store(v);
+    return v;
+}
+
 // |N_d| for an l-mer over a 4-letter alphabet: sum_{i<=d} C(l,i) 3^i (Appendix D).
 double ball_size(int l, int d) {
     double s = 0, c = 1;
@@ -213,6 +226,7 @@ struct pms_batch {
     hipEvent_t ev[6] = {};
     bool timed = false;
     bool ran = false;
+    int plan_status = PMS_OK;  // PMS_E_UNSUPPORTED when the search's LDS does not fit
     int failed = PMS_OK;  // sticky error: the batch's device state is unusable
     int words = 1;
     std::vector<InstCounters> last_ctr;  // counters read back by the last results call
@@ -273,6 +287,17 @@ size_t plan_layout(pms_batch* bt) {
     p.search_blocks = device_cus() * wpc;
     p.compat_kernel = 1;
     p.split = bt->tune.split > 0 ? (int)bt->tune.split : kSplitDefault;
+    // staged survivors per tail batch (LDS per wave grows with it, so it
+    // trades resident waves against checks from HBM): measured on MI355X,
+    // 1024 suits n*(m-l+1) up to about 12000 l-mers per instance, 512 the
+    // batched mix of larger instances
+    if (bt->tune.stage_cap > 0)
+        p.s2cap = std::max(kStageCapMin, std::min(kStageCapMax, (int)(bt->tune.stage_cap + 63) / 64 * 64));
+    else
+        p.s2cap = p.max_n_lmers > 12000 ? 512 : 1024;
+    while (p.s2cap > kStageCapMin && search_lds_bytes(p) > (size_t)device_lds_per_block())
+        p.s2cap = std::max(kStageCapMin, p.s2cap / 2 / 64 * 64);
+    bt->plan_status = search_lds_bytes(p) > (size_t)device_lds_per_block() ? PMS_E_UNSUPPORTED : PMS_OK;
     const int64_t lmer_bytes = bt->words == 1 ? 8 : 16;
     size_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -287,7 +312,6 @@ size_t plan_layout(pms_batch* bt) {
     size_t o_compat = take(compat_off * 8);
     size_t o_items = take((int64_t)bt->item_cap * 8);
     size_t o_parts = take((int64_t)bt->part_cap * 8);
-    size_t o_nodes = take((int64_t)p.search_blocks * kNodeCap * (int64_t)sizeof(Node));
     size_t o_keys = take(out_off * 8 * bt->words);
     size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
     size_t o_q = take(2 * sizeof(QueueCounters));
@@ -299,7 +323,6 @@ size_t plan_layout(pms_batch* bt) {
     bt->b.compat = (uint64_t*)o_compat;
     bt->b.items = (uint64_t*)o_items;
     bt->b.parts = (uint64_t*)o_parts;
-    bt->b.nodes = (Node*)o_nodes;
     bt->b.keys = (uint64_t*)o_keys;
     bt->b.ctr = (InstCounters*)o_ctr;
     bt->b.q = (QueueCounters*)o_q;
@@ -311,23 +334,22 @@ size_t plan_layout(pms_batch* bt) {
 namespace pms {
 
 // Upper bound of the device bytes an instance adds to a batch (16-byte
-// l-mers and 2-word keys, whatever the batch's width).
+// l-mers and 2-word keys, whatever the batch's width; its work items and
+// at most as many part items).
 size_t inst_bytes(int n, int m, int l, int d, const pms_tune* tune) {
     const int64_t r = m >= l ? m - l + 1 : 0;
     const int64_t N = (int64_t)n * r, bw = (r + 63) / 64;
     const int64_t cap = (tune && tune->out_capacity > 0) ? next_pow2(tune->out_capacity)
                                                           : presized_out_cap(n, m, l, d);
     return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 + N * 16 + N * n * bw * 8 +
-                    r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters));
+                    2 * r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters));
 }
 
-// Device bytes of a batch that do not depend on its instances (part queue
-// bound, per-wave node areas, queue counters, region alignment).
+// Device bytes of a batch that do not depend on its instances (the part
+// queue's minimum, queue counters, region alignment).
 size_t fixed_bytes(const pms_tune* tune) {
-    const int wpc = (tune && tune->waves_per_cu > 0) ? tune->waves_per_cu : 20;
-    const int64_t blocks = (int64_t)device_cus() * wpc;
-    return (size_t)(((int64_t)1 << 22) * 8 + blocks * kNodeCap * (int64_t)sizeof(Node) +
-                    2 * (int64_t)sizeof(QueueCounters) + 16 * 256);
+    (void)tune;
+    return (size_t)(1024 * 8 + 2 * (int64_t)sizeof(QueueCounters) + 16 * 256);
 }
 
 }  // namespace pms
@@ -343,7 +365,6 @@ void resolve(pms_batch* bt) {
     bt->b.compat = (uint64_t*)(a + (size_t)bt->b.compat);
     bt->b.items = (uint64_t*)(a + (size_t)bt->b.items);
     bt->b.parts = (uint64_t*)(a + (size_t)bt->b.parts);
-    bt->b.nodes = (Node*)(a + (size_t)bt->b.nodes);
     bt->b.keys = (uint64_t*)(a + (size_t)bt->b.keys);
     bt->b.ctr = (InstCounters*)(a + (size_t)bt->b.ctr);
     bt->b.q = (QueueCounters*)(a + (size_t)bt->b.q);
@@ -364,6 +385,7 @@ void release_arena(pms_batch* bt) {
 // own stream; `uploaded` marks their completion for whichever stream runs.
 int materialise(pms_batch* bt, bool use_cache) {
     const size_t need = plan_layout(bt);
+    if (bt->plan_status) return bt->plan_status;
     bt->arena_bytes = need;
     if (bt->ext_ws) {
         if (bt->ext_ws_bytes < need) return PMS_E_NOMEM;
@@ -431,6 +453,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
             (tune->s1_end > 0 && tune->s1_begin > tune->s1_end))
             return PMS_E_INVAL;
         if (tune->out_capacity < 0) return PMS_E_INVAL;
+        if (tune->stage_cap < 0 || tune->stage_cap > kStageCapMax) return PMS_E_INVAL;
     }
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
@@ -596,8 +619,9 @@ int pms_batch_workspace_size(const pms_instance* inst, int32_t count, const pms_
     int rc = make_batch(inst, count, tune, &bt);
     if (rc) return rc;
     *bytes = plan_layout(bt);
+    rc = bt->plan_status;
     delete bt;
-    return PMS_OK;
+    return rc;
 }
 
 int pms_batch_create(const pms_instance* inst, int32_t count, const pms_tune* tune,

@@ -255,7 +255,8 @@ def test_serving_matches_alone():
 def test_serving_admission_and_errors():
     _say("serving: admission by device memory, invalid requests, poll")
     inst = I.planted(3, 9, 2, 8, 150)
-    srv = pms.Server(device_mem_cap=1 << 20)  # 1 MiB: smaller than any instance's plan
+    one = pms.Batch.workspace_size([pms.Problem(inst.seqs, 9, 2)])
+    srv = pms.Server(device_mem_cap=one // 4)  # smaller than the instance's own plan
     try:
         with pytest.raises(pms.PmsError) as e:
             srv.submit(pms.Problem(inst.seqs, 9, 2))
