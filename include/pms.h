@@ -89,10 +89,11 @@ typedef struct pms_tune {
     int32_t compat_kernel;  /* 1: VALU xor/popcount (the only builder in this
                                version; 2, an int8 one-hot MFMA builder, returns
                                PMS_E_UNSUPPORTED); 0 = 1 */
-    int32_t split;          /* candidates for the third stack member one work
-                               item keeps; the rest become part items of this
-                               many each, searched by a second launch (1..2047;
-                               0 = 16) */
+    int32_t split;          /* survivors of the next member's string one wave
+                               keeps (1..2047; 0 = 16); the rest are queued in
+                               ranges of this size for other waves: at stack
+                               size 2 as part items (a second launch), at 3
+                               and up as deep items (further launches) */
     int32_t s1_begin;       /* search only the S_1 windows [s1_begin, s1_end) */
     int32_t s1_end;         /* (Section 2.3's independent sub-problems).  The
                                result is then the motifs that are within d of
@@ -159,9 +160,11 @@ int pms_batch_destroy(pms_batch* b);
  * compat_pairs is the number of unordered pairs of l-mers from different
  * strings (each one Hamming test of the compatibility matrix, Section 2.1);
  * items are the level-2 work items the expansion queued; motifs_emitted
- * counts motifs before removal of repeats.  The search-side counters
- * (pushes ... verify_tests) are -1: this version does not count them on
- * the device. */
+ * counts motifs before removal of repeats; done_ticks is the device clock
+ * (100 MHz) at which the instance's last search work item finished (0 if
+ * it had none), so differences between instances of one run give their
+ * completion order and spread.  The search-side counters (pushes ...
+ * verify_tests) are -1: they are not counted on the device. */
 typedef struct {
     int64_t compat_pairs;
     int64_t items;
@@ -173,6 +176,7 @@ typedef struct {
     int64_t candidates;
     int64_t verify_tests;
     int64_t motifs_emitted;  /* before removal of repeats */
+    int64_t done_ticks;
 } pms_work;
 int pms_batch_work(pms_batch* b, int32_t instance, pms_work* out);
 

@@ -42,12 +42,28 @@ struct InstDev {
 
 // Per-instance device counters.
 struct InstCounters {
-    unsigned long long out_count;  // motifs emitted (with repeats)
-    unsigned long long uniq;       // distinct motifs after sort/unique
-    unsigned int flags;            // kFlag* bits
+    unsigned long long out_count;    // motifs emitted (with repeats)
+    unsigned long long uniq;         // distinct motifs after sort/unique
+    unsigned int flags;              // kFlag* bits
     unsigned int pad;
-    unsigned long long items;      // level-2 work items produced
+    unsigned long long items;        // level-2 work items produced
+    unsigned long long outstanding;  // items, parts and deep items not finished yet
+    unsigned long long done_at;      // 100 MHz device clock when outstanding reached 0
 };
+
+// Deep item: a stack prefix of k members (string and window of each) and a
+// rank range [ra, rb) of the survivors of string p at level k, searched by
+// whichever wave takes it (it rebuilds the levels by pushing the prefix
+// again).  Waves split an oversized string this way at any stack size >= 3.
+struct DeepItem {
+    uint32_t inst;
+    uint8_t k, p, pad0, pad1;
+    uint16_t ra, rb;
+    uint16_t win[kMaxT];
+    uint8_t row[kMaxT];
+    uint32_t pad2;
+};
+constexpr int kQueues = 4;  // q[0] items, q[1] parts, q[2], q[3] deep items (alternating phases)
 
 constexpr unsigned kFlagOutOverflow = 1u;
 constexpr unsigned kFlagItemOverflow = 2u;
@@ -72,8 +88,10 @@ struct LaunchPlan {
     int words;           // l-mer width (1 or 2)
     int search_blocks;   // persistent grid size
     int compat_kernel;   // 1 VALU
-    int split;           // third stack members one work item keeps
+    int split;           // survivors of one string a wave keeps (the rest: split items)
     int s2cap;           // staged survivors per tail batch (multiple of 64)
+    int deep_phases;     // search launches for deep items (tmax - 3, at least 0)
+    unsigned long long deep_cap;  // deep items per queue
 };
 
 // Device buffers of one planned batch.
@@ -87,7 +105,8 @@ struct DevBufs {
     uint64_t* parts;     // part items (second search launch)
     uint64_t* keys;
     InstCounters* ctr;
-    QueueCounters* q;    // q[0]: items, q[1]: parts
+    QueueCounters* q;    // kQueues counter sets
+    DeepItem* deep[2];   // deep-item queues
 };
 
 // Kernel launchers (pms_kernels.hip).  All enqueue on `stream`.

@@ -69,7 +69,7 @@ __device__ __forceinline__ int wave_min(int x) {
 // --------------------------------------------------------------- reset
 
 __global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigned long long item_cap,
-                        unsigned long long part_cap) {
+                        unsigned long long part_cap, unsigned long long deep_cap) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_inst) {
         ctr[i].out_count = 0;
@@ -77,12 +77,22 @@ __global__ void k_reset(InstCounters* ctr, int n_inst, QueueCounters* q, unsigne
         ctr[i].flags = 0;
         ctr[i].pad = 0;
         ctr[i].items = 0;
+        ctr[i].outstanding = 0;
+        ctr[i].done_at = 0;
     }
-    if (i < 2) {
+    if (i < kQueues) {
         q[i].item_count = 0;
         q[i].item_next = 0;
-        q[i].item_cap = i == 0 ? item_cap : part_cap;
+        q[i].item_cap = i == 0 ? item_cap : i == 1 ? part_cap : deep_cap;
         q[i].pad = 0;
+    }
+}
+
+// Empty deep queue i before a phase appends to it again.
+__global__ void k_reset_queue(QueueCounters* q, int i) {
+    if (threadIdx.x == 0) {
+        q[i].item_count = 0;
+        q[i].item_next = 0;
     }
 }
 
@@ -210,6 +220,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
             else
                 atomicOr(&ctr[inst].flags, kFlagItemOverflow);
             atomicAdd(&ctr[inst].items, 1ull);
+            atomicAdd(&ctr[inst].outstanding, 1ull);
         }
         return;
     }
@@ -232,6 +243,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
     if (lane == 0) {
         base = atomicAdd(&q->item_count, (unsigned long long)total);
         atomicAdd(&ctr[inst].items, (unsigned long long)total);
+        atomicAdd(&ctr[inst].outstanding, (unsigned long long)total);
     }
     base = __shfl(base, 0, 64);
     if (base + (unsigned long long)total > q->item_cap) {
@@ -1155,30 +1167,42 @@ struct Searcher {
     }
 };
 
-// Persistent search over one queue.  phase 0 takes the expansion's items;
-// when the string chosen at stack size 2 has more than `split` survivors,
-// the wave keeps ranks [0, split) and appends part items
-// for the rest to the part queue, which phase 0 never reads.  phase 1 (a
-// second launch after phase 0 has finished) takes the part items.  Every
-// wave leaves when its queue is empty; nothing waits on another wave.
+// Persistent search over one queue.  phase 0 takes the expansion's items
+// (the stack {u1, u2}), phase 1 the part items (the same stack and a rank
+// range of the next member's string), phase >= 2 the deep items (a longer
+// stack prefix and a rank range).  When the string chosen next has more
+// than `split` survivors, the wave keeps ranks [0, split) and queues the
+// rest in ranges of `split`: at stack size 2 (phase 0) as part items, at
+// stack size 3 and up as deep items for the next phase (deep queues
+// alternate between phases).  Each launch drains its queue: every wave
+// leaves when it is empty and nothing waits on another wave.  An
+// instance's outstanding count is raised for every queued item before the
+// item that queues it finishes, so it reaches zero exactly when the
+// instance's search is complete; that wave stamps the completion time.
 template <int W, int TMAX>
 __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts,
                                                const Lm<W>* __restrict__ lmers,
                                                const uint64_t* __restrict__ compat,
                                                const uint64_t* __restrict__ items,
                                                uint64_t* __restrict__ parts,
+                                               DeepItem* __restrict__ deep0,
+                                               DeepItem* __restrict__ deep1,
                                                QueueCounters* __restrict__ qs,
                                                uint64_t* __restrict__ keys,
                                                InstCounters* __restrict__ ctr,
                                                int level_words, int lv_words, int s2cap,
-                                               int phase, int split) {
+                                               int phase, int last_phase, int split) {
     extern __shared__ uint64_t dyn[];
     __shared__ SearchLds<W, TMAX> S;
     __shared__ unsigned cntw[(TMAX + 1) * kMaxN];
+    __shared__ int rct[TMAX + 1], rhi[TMAX + 1];  // rank taken next / rank limit, per level
     const int lane = lane_id();
-    QueueCounters* q = qs + phase;
+    QueueCounters* q = qs + (phase < 2 ? phase : 2 + (phase & 1));
     QueueCounters* qp = qs + 1;
-    const uint64_t* src = phase == 0 ? items : parts;
+    const DeepItem* dsrc = (phase & 1) ? deep1 : deep0;              // phase >= 2
+    DeepItem* ddst = (phase < 2 || (phase & 1)) ? deep0 : deep1;     // next deep phase
+    QueueCounters* qd = qs + ((phase < 2 || (phase & 1)) ? 2 : 3);
+    const bool deep_ok = (phase < 2 ? 2 : phase + 1) <= last_phase;
     const int mw = (W == 1 ? 2 : 1) * s2cap / 64;  // survivor-bit words per slot
     Lm<W>* s2 = reinterpret_cast<Lm<W>*>(dyn + lv_words);
     uint64_t* memb = reinterpret_cast<uint64_t*>(s2 + s2cap);
@@ -1194,13 +1218,28 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         const int it = uni(S.item);
         __syncthreads();
         if (it < 0) break;
-        const uint64_t item = src[it];
-        if (item == kNoItem) continue;
-        const int inst = uni((int)(item >> 43));
-        const int lo = uni((int)((item >> 32) & 0x7FF));
-        const int u1 = uni((int)((item >> 16) & 0xFFFF));
-        const int p2 = uni((int)((item >> 11) & 31));
-        const int x2 = uni((int)(item & 0x7FF));
+        int inst, u1, p2 = 0, x2 = 0, flev = -1, frlo = 0, frhi = 0;
+        const DeepItem* di = dsrc + it;  // phase >= 2 (fields read in place: no local copy)
+        if (phase < 2) {
+            const uint64_t item = (phase == 0 ? items : parts)[it];
+            if (item == kNoItem) continue;
+            inst = uni((int)(item >> 43));
+            const int lo = uni((int)((item >> 32) & 0x7FF));
+            u1 = uni((int)((item >> 16) & 0xFFFF));
+            p2 = uni((int)((item >> 11) & 31));
+            x2 = uni((int)(item & 0x7FF));
+            if (phase == 1) {
+                flev = 2;
+                frlo = lo;
+                frhi = lo + split;
+            }
+        } else {
+            inst = uni((int)di->inst);
+            u1 = uni((int)di->win[0]);
+            flev = uni((int)di->k);
+            frlo = uni((int)di->ra);
+            frhi = uni((int)di->rb);
+        }
         const InstDev I = insts[inst];
         Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
                              compat + I.compat_off, (uint64_t)u1, keys, ctr, lane, cntw,
@@ -1211,19 +1250,40 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
             S.st[0] = sr.L[u1];
             S.rows[1] = (I.n >= 32 ? 0xFFFFFFFFu : ((1u << I.n) - 1u)) & ~1u;
         }
+        if (lane <= TMAX) {
+            rct[lane] = 0;
+            rhi[lane] = 0x7FFFFFFF;
+        }
         __syncthreads();
         const int t = I.t < TMAX ? I.t : TMAX;
-        int k = 2;
-        if (p2 == 0) {  // n == 1: the stack {u1} is complete, nothing to check
-            if (lane == 0) S.rows[1] = 0;
-            __syncthreads();
-            k = 1;
-        } else if (!sr.push_filter(1, p2, x2)) {
-            continue;
+        int k = 2, kmin = 2;
+        bool run = true;
+        if (phase < 2) {
+            if (p2 == 0) {  // n == 1: the stack {u1} is complete, nothing to check
+                if (lane == 0) S.rows[1] = 0;
+                __syncthreads();
+                k = 1;
+            } else {
+                if (lane == 0) {
+                    S.prow[1] = p2;
+                    S.cursor[1] = x2 + 1;
+                }
+                run = sr.push_filter(1, p2, x2);
+            }
+        } else {
+            // rebuild the levels of the deep item's stack prefix
+            for (int j = 1; j < flev && run; j++) {
+                const int rj = uni((int)di->row[j]), wj = uni((int)di->win[j]);
+                if (lane == 0) {
+                    S.prow[j] = rj;
+                    S.cursor[j] = wj + 1;
+                }
+                run = sr.push_filter(j, rj, wj);
+            }
+            k = kmin = flev;
         }
         bool descend = true;
-        int rank2 = 0, rank2_end = 0x7FFFFFFF;  // survivor ranks this item covers at k == 2
-        for (;;) {
+        while (run) {
             if (descend) {
                 int tp = -2, ra = 0, rb = 0;  // tail batch: string (-1: complete stack), ranks
                 int p = 0, cur = 0;
@@ -1231,60 +1291,84 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                     tp = -1;
                 } else {
                     p = uni(sr.choose_row(k));
-                    if (k == 2) {
-                        const int c = uni((int)sr.cnt16(2, p));
-                        if (phase == 0) {
-                            if (c > split) {
-                                const int extra = (c - 1) / split;
-                                unsigned long long base = 0;
-                                if (lane == 0) base = atomicAdd(&qp->item_count, (unsigned long long)extra);
-                                base = __shfl(base, 0, 64);
-                                if (base + (unsigned long long)extra <= qp->item_cap) {
-                                    for (int e = lane; e < extra; e += 64)
-                                        parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
-                                    rank2_end = split;
+                    const int c = uni((int)sr.cnt16(k, p));
+                    int lo = 0, hi = 0x7FFFFFFF;
+                    if (k == flev) {
+                        // the range this part / deep item covers
+                        lo = frlo;
+                        hi = frhi;
+                        flev = -1;
+                        if (lo > 0) {
+                            cur = uni(sr.nth_bit(k, p, lo));
+                            if (cur < 0) cur = 64 * I.bw;
+                        }
+                    } else if (c > split && (k >= 3 ? deep_ok : phase == 0)) {
+                        // keep ranks [0, split), queue the rest
+                        const int extra = (c - 1) / split;
+                        unsigned long long base = 0;
+                        QueueCounters* qq = k == 2 ? qp : qd;
+                        if (lane == 0) base = atomicAdd(&qq->item_count, (unsigned long long)extra);
+                        base = __shfl(base, 0, 64);
+                        if (base + (unsigned long long)extra <= qq->item_cap) {
+                            if (k == 2) {
+                                const uint64_t item = ((uint64_t)inst << 43) | ((uint64_t)u1 << 16) |
+                                                      ((uint64_t)p2 << 11) | (uint64_t)x2;
+                                for (int e = lane; e < extra; e += 64)
+                                    parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
+                            } else {
+                                for (int e = 0; e < extra; e++) {
+                                    DeepItem* o = ddst + base + e;
+                                    if (lane == 0) {
+                                        o->inst = (uint32_t)inst;
+                                        o->k = (uint8_t)k;
+                                        o->p = (uint8_t)p;
+                                        o->ra = (uint16_t)((e + 1) * split);
+                                        o->rb = (uint16_t)min((e + 2) * split, 65535);
+                                    }
+                                    if (lane < k) {
+                                        o->win[lane] = (uint16_t)(lane == 0 ? u1 : S.cursor[lane] - 1);
+                                        o->row[lane] = (uint8_t)(lane == 0 ? 0 : S.prow[lane]);
+                                    }
                                 }
                             }
-                        } else {
-                            rank2 = lo;
-                            rank2_end = lo + split;
-                            cur = uni(sr.nth_bit(2, p, lo));
-                            if (cur < 0) cur = 64 * I.bw;
+                            if (lane == 0) atomicAdd(&ctr[inst].outstanding, (unsigned long long)extra);
+                            hi = split;
                         }
                     }
                     if (k == t - 1) {  // the last member: string p's survivors
                         tp = p;
-                        ra = k == 2 ? rank2 : 0;
-                        rb = k == 2 ? rank2_end : 0x7FFFFFFF;
+                        ra = lo;
+                        rb = hi;
+                    } else if (lane == 0) {
+                        S.prow[k] = p;
+                        S.cursor[k] = cur;
+                        rct[k] = lo;
+                        rhi[k] = hi;
                     }
                 }
                 if (tp != -2) {
                     sr.tail(k, tp, ra, rb);
                     k--;
-                    if (k < 2) break;
+                    if (k < kmin) break;
                     descend = false;
                     continue;
-                }
-                if (lane == 0) {
-                    S.prow[k] = p;
-                    S.cursor[k] = cur;
                 }
                 __syncthreads();
             }
             const int p = uni(S.prow[k]);
             int x = uni(sr.next_bit(k, p, S.cursor[k]));
-            if (k == 2 && x >= 0) {
-                if (rank2 >= rank2_end) x = -1;
-                else rank2++;
-            }
+            if (x >= 0 && uni(rct[k]) >= uni(rhi[k])) x = -1;
             __syncthreads();
             if (x < 0) {
                 k--;
-                if (k < 2) break;
+                if (k < kmin) break;
                 descend = false;
                 continue;
             }
-            if (lane == 0) S.cursor[k] = x + 1;
+            if (lane == 0) {
+                S.cursor[k] = x + 1;
+                rct[k]++;
+            }
             __syncthreads();
             if (sr.push_filter(k, p, x)) {
                 k++;
@@ -1292,6 +1376,11 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
             } else {
                 descend = false;
             }
+        }
+        // this item is done
+        if (lane == 0) {
+            const unsigned long long left = atomicSub(&ctr[inst].outstanding, 1ull);
+            if (left == 1ull) ctr[inst].done_at = (unsigned long long)__builtin_amdgcn_s_memrealtime();
         }
     }
 }
@@ -1432,7 +1521,7 @@ hipError_t launch_reset(const LaunchPlan& p, const DevBufs& b, unsigned long lon
     int blocks = (p.n_inst + 255) / 256;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, stream, b.ctr, p.n_inst, b.q, item_cap,
-                       part_cap);
+                       part_cap, p.deep_cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_parts, dim3(1024), dim3(256), 0, stream, b.parts, part_cap);
@@ -1487,10 +1576,18 @@ template <int W, int TMAX>
 static hipError_t search_t(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
     const size_t lds = search_lds_bytes(p);
     const int lv_words = (p.tmax > 3 ? p.tmax - 2 : 1) * p.level_words;
-    for (int phase = 0; phase < 2; phase++) {
+    const int last = 1 + p.deep_phases;
+    for (int phase = 0; phase <= last; phase++) {
+        if (phase >= 3) {
+            // the deep queue phase - 1 consumed is appended to by this phase
+            hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, stream, b.q, 2 + ((phase - 1) & 1));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL((k_search<W, TMAX>), dim3(p.search_blocks), dim3(64), lds, stream, b.inst,
-                           (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.q, b.keys, b.ctr,
-                           p.level_words, lv_words, p.s2cap, phase, p.split);
+                           (const Lm<W>*)b.lmers, b.compat, b.items, b.parts, b.deep[0], b.deep[1],
+                           b.q, b.keys, b.ctr, p.level_words, lv_words, p.s2cap, phase, last,
+                           p.split);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -138,8 +138,13 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     const size_t o_compat = take((size_t)N * n * bw * 8);
     const size_t o_items = take((size_t)items * 8);
     const size_t o_parts = take((size_t)parts * 8);
+    const int tmax = std::max(2, t);
+    const int deep_phases = tmax > 3 ? tmax - 3 : 0;
+    const unsigned long long deep_cap = deep_phases > 0 ? (1ull << 16) : 1;
+    const size_t o_deep0 = take((size_t)deep_cap * sizeof(DeepItem));
+    const size_t o_deep1 = take((size_t)deep_cap * sizeof(DeepItem));
     const size_t o_ctr = take(sizeof(InstCounters));
-    const size_t o_q = take(2 * sizeof(QueueCounters));
+    const size_t o_q = take(kQueues * sizeof(QueueCounters));
     if (off >= kScratchBytes) return PMS_E_NOMEM;
     // key slots: the rest of the scratch, a power of two (the sort's size)
     int64_t out_cap = 1;
@@ -156,6 +161,8 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     b.compat = (uint64_t*)(s + o_compat);
     b.items = (uint64_t*)(s + o_items);
     b.parts = (uint64_t*)(s + o_parts);
+    b.deep[0] = (DeepItem*)(s + o_deep0);
+    b.deep[1] = (DeepItem*)(s + o_deep1);
     b.keys = (uint64_t*)(s + o_keys);
     b.ctr = (InstCounters*)(s + o_ctr);
     b.q = (QueueCounters*)(s + o_q);
@@ -183,7 +190,9 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     p.max_r = r;
     p.max_n = n;
     p.level_words = std::max(1, n * bw);
-    p.tmax = std::max(2, t);
+    p.tmax = tmax;
+    p.deep_phases = deep_phases;
+    p.deep_cap = deep_cap;
     p.words = words;
     p.search_blocks = blocks;
     p.compat_kernel = 1;

@@ -312,9 +312,21 @@ size_t plan_layout(pms_batch* bt) {
     size_t o_compat = take(compat_off * 8);
     size_t o_items = take((int64_t)bt->item_cap * 8);
     size_t o_parts = take((int64_t)bt->part_cap * 8);
+    // deep items: searches at stack size 3 and up split across waves
+    // (only when some instance's threshold exceeds 3)
+    p.deep_phases = p.tmax > 3 ? p.tmax - 3 : 0;
+    unsigned long long deep_items = 0;  // work items of the instances that can split deeper
+    for (const InstDev& d : bt->dinst)
+        if (d.t > 3) deep_items += (unsigned long long)d.r * (unsigned long long)std::max(d.r, 1);
+    p.deep_cap = p.deep_phases > 0
+                     ? std::min<unsigned long long>(std::max<unsigned long long>(deep_items, 1024) * 2,
+                                                    1ull << 20)
+                     : 1;
+    size_t o_deep0 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
+    size_t o_deep1 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
     size_t o_keys = take(out_off * 8 * bt->words);
     size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
-    size_t o_q = take(2 * sizeof(QueueCounters));
+    size_t o_q = take(kQueues * sizeof(QueueCounters));
     // offsets are stored relative to the arena; resolve later
     bt->b.inst = (InstDev*)o_inst;
     bt->b.chars = (uint8_t*)o_chars;
@@ -323,6 +335,8 @@ size_t plan_layout(pms_batch* bt) {
     bt->b.compat = (uint64_t*)o_compat;
     bt->b.items = (uint64_t*)o_items;
     bt->b.parts = (uint64_t*)o_parts;
+    bt->b.deep[0] = (DeepItem*)o_deep0;
+    bt->b.deep[1] = (DeepItem*)o_deep1;
     bt->b.keys = (uint64_t*)o_keys;
     bt->b.ctr = (InstCounters*)o_ctr;
     bt->b.q = (QueueCounters*)o_q;
@@ -341,15 +355,22 @@ size_t inst_bytes(int n, int m, int l, int d, const pms_tune* tune) {
     const int64_t N = (int64_t)n * r, bw = (r + 63) / 64;
     const int64_t cap = (tune && tune->out_capacity > 0) ? next_pow2(tune->out_capacity)
                                                           : presized_out_cap(n, m, l, d);
+    const int t = (tune && tune->threshold > 0) ? std::max(2, std::min(kMaxT, (int)tune->threshold))
+                                                : pms_default_threshold(n, m, l, d);
+    // deep-item queues exist only in batches with a threshold above 3; two
+    // queues of at most 2 * (sum of r^2, at least 1024) entries
+    const int64_t deep = t > 3 ? 2 * (2 * r * std::max<int64_t>(r, 1) + 2048) * (int64_t)sizeof(DeepItem) : 0;
     return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 + N * 16 + N * n * bw * 8 +
-                    2 * r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters));
+                    2 * r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters) +
+                    deep);
 }
 
 // Device bytes of a batch that do not depend on its instances (the part
 // queue's minimum, queue counters, region alignment).
 size_t fixed_bytes(const pms_tune* tune) {
     (void)tune;
-    return (size_t)(1024 * 8 + 2 * (int64_t)sizeof(QueueCounters) + 16 * 256);
+    return (size_t)(1024 * 8 + kQueues * (int64_t)sizeof(QueueCounters) +
+                    2 * (int64_t)sizeof(DeepItem) + 16 * 256);
 }
 
 }  // namespace pms
@@ -365,6 +386,8 @@ void resolve(pms_batch* bt) {
     bt->b.compat = (uint64_t*)(a + (size_t)bt->b.compat);
     bt->b.items = (uint64_t*)(a + (size_t)bt->b.items);
     bt->b.parts = (uint64_t*)(a + (size_t)bt->b.parts);
+    bt->b.deep[0] = (DeepItem*)(a + (size_t)bt->b.deep[0]);
+    bt->b.deep[1] = (DeepItem*)(a + (size_t)bt->b.deep[1]);
     bt->b.keys = (uint64_t*)(a + (size_t)bt->b.keys);
     bt->b.ctr = (InstCounters*)(a + (size_t)bt->b.ctr);
     bt->b.q = (QueueCounters*)(a + (size_t)bt->b.q);
@@ -742,6 +765,7 @@ int pms_batch_work(pms_batch* bt, int32_t i, pms_work* w) {
     w->pushes = w->filter_words = w->triple_tests = w->tuples = -1;
     w->gen_evals = w->candidates = w->verify_tests = -1;
     w->motifs_emitted = (int64_t)c.out_count;
+    w->done_ticks = (int64_t)c.done_at;
     return PMS_OK;
 }
 

@@ -64,7 +64,7 @@ class Tune(ctypes.Structure):
 class Work(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "compat_pairs", "items", "pushes", "filter_words", "triple_tests", "tuples",
-        "gen_evals", "candidates", "verify_tests", "motifs_emitted")]
+        "gen_evals", "candidates", "verify_tests", "motifs_emitted", "done_ticks")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

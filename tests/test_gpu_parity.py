@@ -71,6 +71,8 @@ def test_plain_gpu_config_seed0(l, d):
     dict(threshold=2), dict(threshold=3), dict(threshold=4), dict(threshold=6),
     dict(triple_filter=-1), dict(lmer_words=2), dict(waves_per_cu=1), dict(out_capacity=1),
     dict(split=1), dict(split=3), dict(split=2047), dict(threshold=4, split=1),
+    dict(threshold=5, split=2), dict(threshold=6, split=1), dict(threshold=4, split=5),
+    dict(stage_cap=512), dict(stage_cap=4096), dict(threshold=5, stage_cap=512, split=3),
 ])
 def test_output_invariant_under_tuning(tune):
     _say(f"tune {tune}")
@@ -88,6 +90,23 @@ def test_batch_equals_alone():
     for x, got in zip(insts, batch):
         assert got == oracle.solve_b(x.seqs, x.l, x.d)
         assert got == _gpu(x)
+
+
+def test_per_instance_completion():
+    """Every instance with search work carries the device time its last work
+    item finished; a deep split run gives the same sets and stamps."""
+    _say("per-instance completion stamps")
+    insts = [I.planted(s, 10, 2, 10, 200) for s in range(3)] + [I.planted(9, 11, 3, 8, 250)]
+    want = [oracle.solve_b(x.seqs, x.l, x.d) for x in insts]
+    for tune in (None, pms.Tune(threshold=4, split=2)):
+        b = pms.Batch([pms.Problem(x.seqs, x.l, x.d) for x in insts], tune=tune)
+        try:
+            b.run()
+            assert b.results() == want
+            ticks = [b.work(i)["done_ticks"] for i in range(len(insts))]
+            assert all(t > 0 for t in ticks), ticks
+        finally:
+            b.close()
 
 
 def test_device_batch_rerun():
