@@ -160,7 +160,23 @@ def hd_compares(insts, units, t_of):
 def run_batched(args, I, pms):
     insts = I.batch_mix(BATCH_SEED0, args.count)
     probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
-    tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc, split=args.split)
+    tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc, split=args.split,
+                    stage_cap=args.stage_cap)
+    default_rate = None
+    if args.autotune:
+        # the autotuner picks the search parameters on a 32-instance sample
+        # of the batch; the defaults are timed once on the whole batch beside
+        # the tuned steps
+        base = tune
+        tune = pms.autotune(probs, base=base, max_runs=args.tune_runs, sample=32)
+        b0 = pms.Batch(probs, tune=base)
+        b0.run()
+        b0.results()
+        t0 = time.perf_counter()
+        b0.run()
+        b0.results()
+        default_rate = len(probs) / (time.perf_counter() - t0)
+        b0.close()
     b = pms.Batch(probs, tune=tune)
     for _ in range(args.warmup):
         b.run()
@@ -191,7 +207,7 @@ def run_batched(args, I, pms):
     b.close()
     plain = None
     if not args.no_plain:
-        singles = [pms.Batch([p], tune=tune) for p in probs]
+        singles = [pms.Batch([p]) for p in probs]  # pms_solve's own setting
         for sb in singles:
             sb.run()
             sb.results()
@@ -204,14 +220,14 @@ def run_batched(args, I, pms):
         plain = time.perf_counter() - tp
         for sb in singles:
             sb.close()
-    return insts, elapsed, phases, plain, graph_rate, [len(r) for r in res]
+    return insts, elapsed, phases, plain, graph_rate, [len(r) for r in res], tune, default_rate
 
 
 def batched_main(args, I, pms):
-    insts, elapsed, phases, plain_s, graph_rate, sizes = run_batched(args, I, pms)
+    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate = run_batched(args, I, pms)
     n = len(insts)
     value = n * args.steps / elapsed
-    t_of = [args.threshold or pms.default_threshold(x.n, x.m, x.l, x.d) for x in insts]
+    t_of = [tune.threshold or pms.default_threshold(x.n, x.m, x.l, x.d) for x in insts]
     wu = load_json("work_units_batched.json")
     units = None
     if wu and len(wu["instances"]) >= n and all(
@@ -253,8 +269,12 @@ def batched_main(args, I, pms):
                                "{(11,3),(13,4),(15,5)}, n in [10,30], m in [300,1000], "
                                f"seeds {BATCH_SEED0}-{BATCH_SEED0 + n - 1}; one step = one "
                                "device pass of the whole batch, inputs resident in HBM",
-                   "instances": n, "threshold": args.threshold or "cost model",
-                   "waves_per_cu": args.wpc or "default", "split": args.split or "default"},
+                   "instances": n,
+                   "tune": {k: v for k, v in pms.tune_dict(tune).items()
+                            if k in ("threshold", "lmer_words", "triple_filter", "waves_per_cu",
+                                     "split", "stage_cap")},
+                   "tuned_by": "pms_autotune (32-instance sample)" if args.autotune else "flags"},
+        "default_tune_instances_per_s": round(default_rate, 3) if default_rate else None,
         "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
         "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
         "graph_instances_per_s": round(graph_rate, 3) if graph_rate else None,
@@ -445,6 +465,10 @@ def main():
     ap.add_argument("--wpc", type=int, default=0, help="persistent search waves per CU (0 = auto)")
     ap.add_argument("--split", type=int, default=0, help="part size (0 = auto)")
     ap.add_argument("--threshold", type=int, default=0, help="stack size t (0 = cost model)")
+    ap.add_argument("--stage-cap", type=int, default=0, help="staged survivors per tail batch")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batched: use the flags / defaults instead of pms_autotune")
+    ap.add_argument("--tune-runs", type=int, default=16, help="autotuner pipeline runs")
     ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--workers", type=int, default=3, help="serving: overlapping passes")
     ap.add_argument("--load", type=float, default=0.7,

@@ -55,7 +55,7 @@ typedef enum {
 
 /* One problem instance (Section 1): n strings of length m, motif length l,
  * distance d.  seqs[i] points at S_{i+1}. */
-typedef struct {
+typedef struct pms_instance {
     const char* const* seqs;
     int32_t n;
     int32_t m;
@@ -110,6 +110,22 @@ typedef struct pms_tune {
                                number of motifs (pms_expected_motifs) */
 } pms_tune;
 
+/* Autotuner.  Times the device pipeline on an evenly spread sample of at
+ * most `sample` of the instances (0 = 32) for candidate settings --
+ * staged survivors per tail batch, part size, waves per CU, threshold t
+ * (which Section 2.2 and Appendix D leave to measurement), the Theorem 1
+ * filter, the l-mer width -- one parameter at a time from `base` (NULL =
+ * the defaults), at most max_runs pipeline runs (0 = 16), keeping a change
+ * only when it is at least 2% faster, and writes the best setting to out.
+ * No setting changes the motif sets; a candidate whose counts differ from
+ * the base's is rejected.  The result is cached for batches of the same
+ * shape (the distinct (l, d, n/8, m/256) of the instances and log2 of their
+ * number), in the process and in the file PMS_TUNE_CACHE names if set;
+ * pms_solve_batch / pms_batch_create / pms_batch_workspace_size with
+ * tune == NULL use it.  Blocks; uses the device. */
+int pms_autotune(const pms_instance* inst, int32_t count, const pms_tune* base, int32_t max_runs,
+                 int32_t sample, pms_tune* out);
+
 /* Solve one instance (Section 1 problem statement).  Blocks until done. */
 int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabet,
               int32_t l, int32_t d, pms_result* out);
@@ -119,7 +135,8 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabe
  * queue (two launches: the level-2 work items, then the parts of items too
  * large for one wave), one sort/unique launch, all enqueued back to back on
  * hip_stream (NULL = a stream of the library's own).  outs[i] receives
- * instance i's set.  tune may be NULL.  At most 2^21 instances per call
+ * instance i's set.  tune may be NULL (the autotuner's cached setting for
+ * this shape of batch, else the defaults).  At most 2^21 instances per call
  * (PMS_E_UNSUPPORTED beyond). */
 int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
                     const pms_tune* tune, void* hip_stream);

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpms.so")
-SOURCES = ["pms_kernels.hip", "pms_runtime.cpp", "pms_serve.cpp", "pms_noalloc.hip"]
+SOURCES = ["pms_kernels.hip", "pms_runtime.cpp", "pms_serve.cpp", "pms_tune.cpp", "pms_noalloc.hip"]
 ARCH = os.environ.get("PMS_OFFLOAD_ARCH", "gfx950")
 
 

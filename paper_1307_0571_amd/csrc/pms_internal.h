@@ -4,7 +4,8 @@
 
 #include <hip/hip_runtime_api.h>
 
-struct pms_tune;  // include/pms.h
+struct pms_tune;      // include/pms.h
+struct pms_instance;
 
 namespace pms {
 
@@ -123,5 +124,8 @@ size_t search_lds_bytes(const LaunchPlan& p);
 // fixed_bytes(tune) + the sum of inst_bytes(...) over its instances.
 size_t inst_bytes(int n, int m, int l, int d, const ::pms_tune* tune);
 size_t fixed_bytes(const ::pms_tune* tune);
+
+// The autotuner's cached setting for a batch of this shape (pms_tune.cpp).
+bool tuned_for(const ::pms_instance* inst, int count, ::pms_tune* out);
 
 }  // namespace pms

@@ -481,6 +481,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
     if (tune) bt->tune = *tune;
+    else (void)pms::tuned_for(inst, count, &bt->tune);  // the autotuner's choice for this shape
     bt->hin.resize(count);
     bt->out_cap.assign(count, kOutCapMin);
     bool wide = bt->tune.lmer_words == 2;

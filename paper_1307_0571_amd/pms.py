@@ -126,6 +126,8 @@ def load():
     lib.pms_strerror.argtypes = [ctypes.c_int]
     lib.pms_strerror.restype = ctypes.c_char_p
     lib.pms_version.restype = ctypes.c_char_p
+    lib.pms_autotune.argtypes = [P(_Instance), ctypes.c_int32, P(Tune), ctypes.c_int32,
+                                 ctypes.c_int32, P(Tune)]
     lib.pms_default_threshold.argtypes = [ctypes.c_int] * 4
     lib.pms_expected_motifs.argtypes = [ctypes.c_int] * 4
     lib.pms_expected_motifs.restype = ctypes.c_double
@@ -135,7 +137,7 @@ def load():
               "pms_batch_run", "pms_batch_results", "pms_batch_timings", "pms_batch_destroy",
               "pms_stream_create", "pms_stream_submit", "pms_stream_poll", "pms_stream_wait",
               "pms_stream_destroy", "pms_default_threshold", "pms_batch_work",
-              "pms_device_count", "pms_device_synchronize"):
+              "pms_device_count", "pms_device_synchronize", "pms_autotune"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -205,6 +207,21 @@ def _take(res: _Result) -> List[str]:
 def _check(rc: int, what: str):
     if rc != PMS_OK:
         raise PmsError(rc, what)
+
+
+def autotune(problems: Sequence[Problem], base: Optional[Tune] = None, max_runs: int = 16,
+             sample: int = 32) -> Tune:
+    """pms_autotune: the fastest setting for this shape of batch (cached for
+    later tune=None calls on batches of the same shape)."""
+    mar = _Marshal(problems)
+    out = Tune()
+    _check(load().pms_autotune(mar.arr, mar.count, ctypes.byref(base) if base else None,
+                               max_runs, sample, ctypes.byref(out)), "pms_autotune")
+    return out
+
+
+def tune_dict(t: Tune) -> dict:
+    return {n: int(getattr(t, n)) for n, _ in Tune._fields_ if n != "pad0"}
 
 
 def solve(seqs: Sequence[str], l: int, d: int, alphabet: str = "ACGT") -> List[str]:

@@ -92,6 +92,20 @@ def test_batch_equals_alone():
         assert got == _gpu(x)
 
 
+def test_autotune_then_cached(tmp_path, monkeypatch):
+    """The autotuner returns a setting that gives the oracle's sets, writes
+    it to the cache file, and tune=None batches of the same shape use it."""
+    _say("autotune on a small mixed batch")
+    insts = I.batch_mix(1000, 6, ld=((9, 2), (11, 3)), n_range=(6, 10), m_range=(150, 300))
+    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+    want = [oracle.solve_b(x.seqs, x.l, x.d) for x in insts]
+    t = pms.autotune(probs, max_runs=6, sample=6)
+    d = pms.tune_dict(t)
+    assert d["s1_begin"] == 0 and d["s1_end"] == 0
+    assert pms.solve_batch(probs, tune=t) == want
+    assert pms.solve_batch(probs) == want  # tune=None: the cached setting
+
+
 def test_per_instance_completion():
     """Every instance with search work carries the device time its last work
     item finished; a deep split run gives the same sets and stamps."""

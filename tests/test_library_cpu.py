@@ -113,3 +113,13 @@ def test_tune_validation_is_host_only(lib):
     assert st(split=2048) == pms.PMS_E_INVAL
     assert st(split=1) == pms.PMS_OK
     assert st(compat_kernel=2) == pms.PMS_E_UNSUPPORTED       # no MFMA builder in this version
+
+
+def test_autotune_argument_checks(lib):
+    out = pms.Tune()
+    base = pms.Tune(split=7)
+    # no instances: the base comes back, nothing runs on a device
+    assert lib.pms_autotune(None, 0, ctypes.byref(base), 4, 4, ctypes.byref(out)) == pms.PMS_OK
+    assert out.split == 7
+    assert lib.pms_autotune(None, 1, None, 4, 4, ctypes.byref(out)) == pms.PMS_E_INVAL
+    assert lib.pms_autotune(None, 0, None, 4, 4, None) == pms.PMS_E_INVAL
