@@ -22,7 +22,7 @@
  *    (DNA: "ACGT"); characters are case-sensitive.  Codes are assigned in
  *    ascending ASCII order, so the result order is byte order of the motifs.
  *  - Limits of the GPU path: 1 <= l <= 64, 0 <= d < l, 1 <= n <= 32,
- *    m - l + 1 <= 2048.  m < l is valid and yields the empty set.
+ *    m - l + 1 <= 8192.  m < l is valid and yields the empty set.
  *  - Inputs are caller-owned and read only during the call (create/submit
  *    copy them).  Results are library-allocated host memory released with
  *    pms_result_free().  A hip_stream argument is borrowed (NULL = the
@@ -104,7 +104,11 @@ typedef struct pms_tune {
                                for one tail batch (512..4096, rounded up to a
                                multiple of 64; 0 = by the batch's sizes);
                                larger sets are checked from the level bitsets */
-    int32_t pad0;
+    int32_t compat_mode;    /* 1: the whole compat bit-matrix; 2: only the rows
+                               of S_1's l-mers (n times less memory; every push
+                               tests Hd <= 2d on the survivors directly, the
+                               long-sequence mode); 0 = 2 for an instance
+                               whose whole matrix exceeds 1 GiB, else 1 */
     int64_t out_capacity;   /* motif slots per instance (before removal of
                                repeats); 0 = sized from the Appendix C expected
                                number of motifs (pms_expected_motifs) */
@@ -136,7 +140,7 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabe
  * large for one wave), one sort/unique launch, all enqueued back to back on
  * hip_stream (NULL = a stream of the library's own).  outs[i] receives
  * instance i's set.  tune may be NULL (the autotuner's cached setting for
- * this shape of batch, else the defaults).  At most 2^21 instances per call
+ * this shape of batch, else the defaults).  At most 2^20 - 1 instances per call
  * (PMS_E_UNSUPPORTED beyond). */
 int pms_solve_batch(const pms_instance* inst, int32_t count, pms_result* outs,
                     const pms_tune* tune, void* hip_stream);
@@ -245,6 +249,9 @@ int pms_stream_destroy(pms_stream* s);
  *             PMS_E_ALPHABET (a window holds a character outside the
  *             alphabet), PMS_E_NOMEM (more motifs than keys_cap, or more
  *             emitted motifs than the scratch's key slots).
+ * An instance whose whole compat bit-matrix would take over a quarter of the
+ * array keeps only the rows of S_1's l-mers (pms_tune.compat_mode 2); its
+ * work items take (m-l+1)^2 * 8 bytes, so m-l+1 stays below about 5000.
  * Returns PMS_E_INVAL / PMS_E_ALPHABET / PMS_E_UNSUPPORTED as pms_solve does
  * for bad arguments, PMS_E_NOMEM when the instance's buffers do not fit in
  * the scratch array (nothing is enqueued then), PMS_E_DEVICE on a launch

@@ -11,19 +11,27 @@ namespace pms {
 
 // Limits of the device path.
 constexpr int kMaxN = 32;        // strings per instance (row bit masks are 32-bit)
-constexpr int kMaxR = 2048;      // windows per string (11-bit window index)
+constexpr int kMaxR = 8192;      // windows per string (13-bit window index)
 constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes)
 constexpr int kMaxT = 8;         // stack size at which generation starts
 constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
 constexpr int kStageCapMin = 512;   // staged survivors of one tail batch (LDS entries)
 constexpr int kStageCapMax = 4096;
-constexpr int kMaxInst = 1 << 21;  // instances per batch (21-bit field of a work item)
+constexpr int kMaxInst = (1 << 20) - 1;  // instances per batch (20-bit field of a work item)
 
-// Work item (64 bits): inst << 43 | lo << 32 | u1 << 16 | p2 << 11 | x2.
+// Work item (64 bits): inst << 44 | lo << 31 | u1 << 18 | p2 << 13 | x2.
 // u1: window of string 0 (level 1); p2, x2: string and window of the second
 // stack member (p2 == 0 marks n == 1); lo: first rank, among the survivors
 // of the string chosen at stack size 2, that the item covers (0 for the
 // items the expansion writes; part items cover `split` ranks from lo).
+constexpr uint64_t make_item(uint64_t inst, uint64_t lo, uint64_t u1, uint64_t p2, uint64_t x2) {
+    return (inst << 44) | (lo << 31) | (u1 << 18) | (p2 << 13) | x2;
+}
+constexpr int item_inst(uint64_t it) { return (int)(it >> 44); }
+constexpr int item_lo(uint64_t it) { return (int)((it >> 31) & 0x1FFF); }
+constexpr int item_u1(uint64_t it) { return (int)((it >> 18) & 0x1FFF); }
+constexpr int item_p2(uint64_t it) { return (int)((it >> 13) & 31); }
+constexpr int item_x2(uint64_t it) { return (int)(it & 0x1FFF); }
 constexpr uint64_t kNoItem = ~0ull;  // part slot that was reserved but not written
 
 // One instance as the kernels see it.
@@ -34,9 +42,11 @@ struct InstDev {
     int32_t t;        // stack size at which neighbourhood generation starts
     int32_t triple;   // Theorem 1 survivor filter on/off
     int32_t s1_lo, s1_hi;  // S_1 windows searched: [s1_lo, s1_hi)
+    int32_t c1only;   // compat rows only for the l-mers of S_1; pushes test Hd <= 2d directly
+    int32_t pad;
     int64_t chars_off;   // byte offset of the n*m characters
     int64_t lmer_off;    // l-mer offset (units of one packed l-mer)
-    int64_t compat_off;  // u64 offset of the compat bit-matrix [N][n][bw]
+    int64_t compat_off;  // u64 offset of the compat bit-matrix [N][n][bw] (c1only: [r][n][bw])
     int64_t out_off;     // key offset (units of one key)
     int64_t out_cap;     // key slots (power of two)
 };

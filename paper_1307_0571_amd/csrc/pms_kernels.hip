@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
     const InstDev I = insts[blockIdx.y];
     const int N = I.n * I.r;
     if (N <= 0) return;
-    const int ntile = (N + kCompatTile - 1) / kCompatTile;
+    const int Nu = I.c1only ? I.r : N;  // rows computed: every l-mer, or those of S_1
+    const int ntile = (Nu + kCompatTile - 1) / kCompatTile;
     const int task = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     if (task >= ntile * I.n) return;
     const int lane = lane_id();
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
 #pragma unroll
     for (int k = 0; k < kCompatTile; k++) {
         int g = u0 + k;
-        if (g < N) {
+        if (g < Nu) {
             u[k] = L[g];
             urow[k] = g / I.r;
         } else {
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
         if (lane == 0) {
             unsigned long long at = atomicAdd(&q->item_count, 1ull);
             if (at < q->item_cap)
-                items[at] = ((uint64_t)inst << 43) | ((uint64_t)u1 << 16);
+                items[at] = make_item((uint64_t)inst, 0, (uint64_t)u1, 0, 0);
             else
                 atomicOr(&ctr[inst].flags, kFlagItemOverflow);
             atomicAdd(&ctr[inst].items, 1ull);
@@ -261,8 +262,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
             const int b = __builtin_ctzll(bits);
             bits &= bits - 1;
             const uint64_t x2 = (uint64_t)(w * 64 + b);
-            items[base + o++] =
-                ((uint64_t)inst << 43) | ((uint64_t)u1 << 16) | ((uint64_t)p2 << 11) | x2;
+            items[base + o++] = make_item((uint64_t)inst, 0, (uint64_t)u1, (uint64_t)p2, x2);
         }
         done += __shfl(incl, 63, 64);
     }
@@ -364,7 +364,7 @@ struct Searcher {
     InstCounters* ctr;
     int lane;
     unsigned* cntw;
-    int inv_bw;           // ceil(65536 / bw)
+    uint32_t inv_bw;      // ceil(2^32 / bw) (bw >= 2)
     Lm<W>* s2;            // staged survivors (and the filter's listing scratch)
     uint64_t* memb;       // [kTailSlots][mw] survivor bits per slot
     Lm<W>* ut;            // [kTailSlots] candidate of each slot
@@ -378,10 +378,10 @@ struct Searcher {
     __device__ __forceinline__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
     __device__ __forceinline__ unsigned cnt16(int k, int j) { return cntw[k * kMaxN + j]; }
 
-    // string index of flattened row word i (i < n * bw <= 1024): an exact
-    // reciprocal multiply instead of a division
+    // string index of flattened row word i (i < n * bw <= 4096): an exact
+    // reciprocal multiply instead of a division (i * bw < 2^32)
     __device__ __forceinline__ int row_of(int i) const {
-        return (int)(((unsigned)i * (unsigned)inv_bw) >> 16);
+        return I.bw == 1 ? i : (int)__umulhi((unsigned)i, inv_bw);
     }
 
     // Push the window px of string prow as stack member k (stack size becomes
@@ -403,7 +403,7 @@ struct Searcher {
         if (lane < kMaxN) cntw[(k + 1) * kMaxN + lane] = 0u;
         const uint32_t rows = S.rows[k] & ~(1u << prow);
         __syncthreads();
-        const uint64_t* Cu = C + (int64_t)ug * n * bw;
+        const uint64_t* Cu = I.c1only ? C : C + (int64_t)ug * n * bw;  // unused when c1only
         if (k == 1)
             filter_body(C + (int64_t)u1g * n * bw, Cu, top, k, rows);
         else
@@ -438,13 +438,17 @@ struct Searcher {
             ea[a] = S.E[aa][k];
             ha[a] = S.HD[aa][k];
         }
+        // without the compat rows of the other strings (c1only), every parent
+        // survivor is listed and tested for Hd(top, v) <= 2d directly
+        const bool fly = I.c1only != 0;
+        const int d2 = 2 * I.d;
         for (int i0 = 0; i0 < total; i0 += 64) {
             const int i = i0 + lane;
             const int j = row_of(i);
             const bool act = i < total && ((rows >> j) & 1u);
-            const uint64_t nb = act ? (parent[i] & Cu[i]) : 0ull;
+            const uint64_t nb = act ? (fly ? parent[i] : (parent[i] & Cu[i])) : 0ull;
             if (act) child[i] = nb;
-            if (!I.triple) continue;
+            if (!I.triple && !fly) continue;
             const int c = pc(nb);
             const int incl = wave_incl_scan(c);
             const int T = __shfl(incl, 63, 64);
@@ -484,12 +488,14 @@ struct Searcher {
                     for (int u = 0; u < 4; u++) {
                         if (e[u] < 0) continue;
                         const int hv = pc(dmask(top, v[u]));
-                        bool ok = true;
+                        bool ok = !fly || hv <= d2;
+                        if (I.triple) {
 #pragma unroll
-                        for (int a = 0; a < TMAX; a++) {
-                            if (a < k) {
-                                const M da = dmask(sa[a], v[u]);
-                                ok &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
+                            for (int a = 0; a < TMAX; a++) {
+                                if (a < k) {
+                                    const M da = dmask(sa[a], v[u]);
+                                    ok &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
+                                }
                             }
                         }
                         if (!ok)
@@ -520,22 +526,28 @@ struct Searcher {
 
     // window of the survivor of rank nth (0-based) of string p at level k,
     // or -1 if the string has no more survivors; lanes hold one word each
-    // (bw <= 32)
+    // per block of 64 words
     __device__ __forceinline__ int nth_bit(int k, int p, int nth) {
         const uint64_t* row = level(k) + p * I.bw;
-        const uint64_t w = lane < I.bw ? row[lane] : 0ull;
-        const int c = pc(w);
-        const int incl = wave_incl_scan(c);
-        const unsigned long long m = ballot(incl - c <= nth && nth < incl);
-        if (m == 0ull) return -1;
-        const int src = __builtin_ctzll(m);
-        int res = -1;
-        if (lane == src) {
-            uint64_t x = w;
-            for (int i = incl - c; i < nth; i++) x &= x - 1;
-            res = lane * 64 + __builtin_ctzll(x);
+        int done = 0;
+        for (int w0 = 0; w0 < I.bw; w0 += 64) {
+            const uint64_t w = w0 + lane < I.bw ? row[w0 + lane] : 0ull;
+            const int c = pc(w);
+            const int incl = done + wave_incl_scan(c);
+            const unsigned long long m = ballot(incl - c <= nth && nth < incl);
+            if (m != 0ull) {
+                const int src = __builtin_ctzll(m);
+                int res = -1;
+                if (lane == src) {
+                    uint64_t x = w;
+                    for (int i = incl - c; i < nth; i++) x &= x - 1;
+                    res = (w0 + lane) * 64 + __builtin_ctzll(x);
+                }
+                return __shfl(res, src, 64);
+            }
+            done = __shfl(incl, 63, 64);
         }
-        return __shfl(res, src, 64);
+        return -1;
     }
 
     // next survivor of string p at level k with window >= from, or -1
@@ -669,20 +681,23 @@ struct Searcher {
     // (b - a <= kTailSlots) into S.xs; returns how many.
     __device__ __forceinline__ int list_candidates(int k, int p, int a, int b) {
         const uint64_t* row = level(k) + p * I.bw;
-        const uint64_t w = lane < I.bw ? row[lane] : 0ull;
-        const int c = pc(w);
-        const int incl = wave_incl_scan(c);
-        const int tot = __shfl(incl, 63, 64);
-        const int hi = b < tot ? b : tot;
-        int rank = incl - c;
-        uint64_t bits = w;
-        while (bits && rank < hi) {
-            const int bb = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            if (rank >= a) S.xs[rank - a] = lane * 64 + bb;
-            rank++;
+        int done = 0;
+        for (int w0 = 0; w0 < I.bw && done < b; w0 += 64) {
+            const uint64_t w = w0 + lane < I.bw ? row[w0 + lane] : 0ull;
+            const int c = pc(w);
+            const int incl = done + wave_incl_scan(c);
+            int rank = incl - c;
+            uint64_t bits = w;
+            while (bits && rank < b) {
+                const int bb = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                if (rank >= a) S.xs[rank - a] = (w0 + lane) * 64 + bb;
+                rank++;
+            }
+            done = __shfl(incl, 63, 64);
         }
         __syncthreads();
+        const int hi = b < done ? b : done;
         return hi > a ? hi - a : 0;
     }
 
@@ -1223,11 +1238,11 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         if (phase < 2) {
             const uint64_t item = (phase == 0 ? items : parts)[it];
             if (item == kNoItem) continue;
-            inst = uni((int)(item >> 43));
-            const int lo = uni((int)((item >> 32) & 0x7FF));
-            u1 = uni((int)((item >> 16) & 0xFFFF));
-            p2 = uni((int)((item >> 11) & 31));
-            x2 = uni((int)(item & 0x7FF));
+            inst = uni(item_inst(item));
+            const int lo = uni(item_lo(item));
+            u1 = uni(item_u1(item));
+            p2 = uni(item_p2(item));
+            x2 = uni(item_x2(item));
             if (phase == 1) {
                 flev = 2;
                 frlo = lo;
@@ -1243,7 +1258,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         const InstDev I = insts[inst];
         Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
                              compat + I.compat_off, (uint64_t)u1, keys, ctr, lane, cntw,
-                             (65536 + I.bw - 1) / (I.bw > 0 ? I.bw : 1),
+                             I.bw > 1 ? (uint32_t)((0xFFFFFFFFull + (uint64_t)I.bw) / (uint64_t)I.bw) : 0u,
                              s2, memb, ut, leaf, leafslot, s2cap, mw, W == 1 && I.l <= 16,
                              (W == 1 && I.l <= 16) ? 2 * s2cap : s2cap};
         if (lane == 0) {
@@ -1311,10 +1326,9 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                         base = __shfl(base, 0, 64);
                         if (base + (unsigned long long)extra <= qq->item_cap) {
                             if (k == 2) {
-                                const uint64_t item = ((uint64_t)inst << 43) | ((uint64_t)u1 << 16) |
-                                                      ((uint64_t)p2 << 11) | (uint64_t)x2;
                                 for (int e = lane; e < extra; e += 64)
-                                    parts[base + e] = item | ((uint64_t)((e + 1) * split) << 32);
+                                    parts[base + e] = make_item((uint64_t)inst, (uint64_t)((e + 1) * split),
+                                                                (uint64_t)u1, (uint64_t)p2, (uint64_t)x2);
                             } else {
                                 for (int e = 0; e < extra; e++) {
                                     DeepItem* o = ddst + base + e;

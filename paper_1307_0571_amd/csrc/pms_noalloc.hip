@@ -135,7 +135,10 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     const size_t o_inst = take(sizeof(InstDev));
     const size_t o_lut = take(256);
     const size_t o_lmers = take((size_t)N * (words == 1 ? 8 : 16));
-    const size_t o_compat = take((size_t)N * n * bw * 8);
+    // the whole compat matrix when it takes at most a quarter of the scratch,
+    // else only the rows of S_1's l-mers (pushes test Hd <= 2d directly)
+    const int c1only = (size_t)N * n * bw * 8 > kScratchBytes / 4 ? 1 : 0;
+    const size_t o_compat = take((size_t)(c1only ? r : N) * n * bw * 8);
     const size_t o_items = take((size_t)items * 8);
     const size_t o_parts = take((size_t)parts * 8);
     const int tmax = std::max(2, t);
@@ -178,6 +181,7 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     v.triple = 1;
     v.s1_lo = 0;
     v.s1_hi = r;
+    v.c1only = c1only;
     v.chars_off = 0;
     v.lmer_off = 0;
     v.compat_off = 0;

@@ -124,8 +124,12 @@ int64_t presized_out_cap(int n, int m, int l, int d) {
     return next_pow2(std::max(kOutCapMin, c));
 }
 
+// An instance whose whole compat matrix would exceed this keeps only the
+// rows of S_1's l-mers (n times smaller); its pushes test Hd <= 2d directly.
+constexpr int64_t kCompatBudget = int64_t(1) << 30;
+
 struct HostInst {
-    int n, m, l, d, t, triple, s1_lo, s1_hi;
+    int n, m, l, d, t, triple, s1_lo, s1_hi, c1only;
     std::string alpha;  // sorted
 };
 
@@ -263,6 +267,8 @@ size_t plan_layout(pms_batch* bt) {
         d.triple = h.triple;
         d.s1_lo = h.s1_lo;
         d.s1_hi = h.s1_hi;
+        d.c1only = h.c1only;
+        d.pad = 0;
         d.chars_off = chars_off;
         d.lmer_off = lmer_off;
         d.compat_off = compat_off;
@@ -271,7 +277,7 @@ size_t plan_layout(pms_batch* bt) {
         const int64_t N = (int64_t)d.n * d.r;
         chars_off += (int64_t)h.n * h.m;
         lmer_off += N;
-        compat_off += N * d.n * d.bw;
+        compat_off += (d.c1only ? (int64_t)d.r : N) * d.n * d.bw;
         out_off += d.out_cap;
         items += (unsigned long long)d.r * (unsigned long long)std::max(d.r, 1);
         p.max_n_lmers = std::max<int64_t>(p.max_n_lmers, N);
@@ -477,6 +483,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
             return PMS_E_INVAL;
         if (tune->out_capacity < 0) return PMS_E_INVAL;
         if (tune->stage_cap < 0 || tune->stage_cap > kStageCapMax) return PMS_E_INVAL;
+        if (tune->compat_mode < 0 || tune->compat_mode > 2) return PMS_E_INVAL;
     }
     pms_batch* bt = new (std::nothrow) pms_batch();
     if (!bt) return PMS_E_NOMEM;
@@ -500,6 +507,8 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         h.s1_hi = all ? r : std::min(r, (int)bt->tune.s1_end);
         h.s1_lo = all ? 0 : std::min(h.s1_hi, (int)bt->tune.s1_begin);
         if (h.l > 32) wide = true;
+        const int64_t full = (int64_t)h.n * r * h.n * ((r + 63) / 64) * 8;
+        h.c1only = bt->tune.compat_mode == 2 || (bt->tune.compat_mode == 0 && full > kCompatBudget);
         bt->out_cap[i] = bt->tune.out_capacity > 0 ? next_pow2(bt->tune.out_capacity)
                                                    : presized_out_cap(h.n, h.m, h.l, h.d);
     }

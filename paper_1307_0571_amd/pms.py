@@ -52,13 +52,14 @@ class Tune(ctypes.Structure):
                 ("triple_filter", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("compat_kernel", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("s1_begin", ctypes.c_int32), ("s1_end", ctypes.c_int32),
-                ("stage_cap", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("stage_cap", ctypes.c_int32), ("compat_mode", ctypes.c_int32),
                 ("out_capacity", ctypes.c_int64)]
 
     def __init__(self, threshold=0, lmer_words=0, triple_filter=0, waves_per_cu=0,
-                 compat_kernel=0, split=0, s1_begin=0, s1_end=0, out_capacity=0, stage_cap=0):
+                 compat_kernel=0, split=0, s1_begin=0, s1_end=0, out_capacity=0, stage_cap=0,
+                 compat_mode=0):
         super().__init__(threshold, lmer_words, triple_filter, waves_per_cu, compat_kernel,
-                         split, s1_begin, s1_end, stage_cap, 0, out_capacity)
+                         split, s1_begin, s1_end, stage_cap, compat_mode, out_capacity)
 
 
 class Work(ctypes.Structure):
@@ -221,7 +222,7 @@ def autotune(problems: Sequence[Problem], base: Optional[Tune] = None, max_runs:
 
 
 def tune_dict(t: Tune) -> dict:
-    return {n: int(getattr(t, n)) for n, _ in Tune._fields_ if n != "pad0"}
+    return {n: int(getattr(t, n)) for n, _ in Tune._fields_}
 
 
 def solve(seqs: Sequence[str], l: int, d: int, alphabet: str = "ACGT") -> List[str]:

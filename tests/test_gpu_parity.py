@@ -73,6 +73,8 @@ def test_plain_gpu_config_seed0(l, d):
     dict(split=1), dict(split=3), dict(split=2047), dict(threshold=4, split=1),
     dict(threshold=5, split=2), dict(threshold=6, split=1), dict(threshold=4, split=5),
     dict(stage_cap=512), dict(stage_cap=4096), dict(threshold=5, stage_cap=512, split=3),
+    dict(compat_mode=1), dict(compat_mode=2), dict(compat_mode=2, triple_filter=-1),
+    dict(compat_mode=2, threshold=5, split=2), dict(compat_mode=2, threshold=2),
 ])
 def test_output_invariant_under_tuning(tune):
     _say(f"tune {tune}")
@@ -266,6 +268,31 @@ def test_limit_sizes_vs_oracle(name, seed, l, d, n, m):
     inst = I.planted(seed, l, d, n, m)
     want = oracle.solve_a(inst.seqs, l, d)
     got = _gpu(inst)
+    assert got == want
+    assert inst.motif in got
+
+
+# Long strings: 8192 windows per string (128 words per row bitset).  The
+# first keeps the whole compat matrix (302 MB); the second's would take
+# 1.2 GiB, so only S_1's rows are built and every push tests Hd <= 2d on the
+# survivors directly; the third forces that mode on the first instance.
+_LONG_WANT = {}
+
+
+@pytest.mark.parametrize("name,seed,l,d,n,m,solver,tune", [
+    ("r8192_12_2", 50, 12, 2, 6, 8203, "b", None),
+    ("r8192_n12_auto_s1_rows", 47, 9, 1, 12, 8200, "a", None),
+    ("r8192_12_2_s1_rows", 50, 12, 2, 6, 8203, "b", dict(compat_mode=2)),
+])
+def test_long_sequences_vs_oracle(name, seed, l, d, n, m, solver, tune):
+    _say(f"{name}: seed={seed} l={l} d={d} n={n} m={m} tune={tune}")
+    inst = I.planted(seed, l, d, n, m)
+    key = (seed, l, d, n, m)
+    if key not in _LONG_WANT:
+        f = oracle.solve_a if solver == "a" else oracle.solve_b
+        _LONG_WANT[key] = f(inst.seqs, l, d)
+    want = _LONG_WANT[key]
+    got = _gpu(inst, pms.Tune(**tune) if tune else None)
     assert got == want
     assert inst.motif in got
 

@@ -65,8 +65,8 @@ def test_rejects_invalid_input(lib):
     assert _status(["A" * 80, "C" * 80], 65, 3) == pms.PMS_E_UNSUPPORTED   # l > 64
     many = I.random_strings(1, 33, 20).seqs
     assert _status(many, 5, 1) == pms.PMS_E_UNSUPPORTED                   # n > 32
-    long = I.random_strings(2, 2, 2100).seqs
-    assert _status(long, 10, 2) == pms.PMS_E_UNSUPPORTED                  # m - l + 1 > 2048
+    long = I.random_strings(2, 2, 8210).seqs
+    assert _status(long, 10, 2) == pms.PMS_E_UNSUPPORTED                  # m - l + 1 > 8192
 
 
 def test_null_arguments(lib):
@@ -113,6 +113,8 @@ def test_tune_validation_is_host_only(lib):
     assert st(split=2048) == pms.PMS_E_INVAL
     assert st(split=1) == pms.PMS_OK
     assert st(compat_kernel=2) == pms.PMS_E_UNSUPPORTED       # no MFMA builder in this version
+    assert st(compat_mode=2) == pms.PMS_OK
+    assert st(compat_mode=3) == pms.PMS_E_INVAL
 
 
 def test_autotune_argument_checks(lib):

@@ -106,12 +106,24 @@ def test_noalloc_wide_lmers_and_stream():
         hip_rt.stream_destroy(st)
 
 
+def test_noalloc_s1_rows_mode():
+    # the whole compat matrix (130 MB) would take over a quarter of the
+    # scratch array, so only S_1's rows are built
+    inst = I.planted(13, 9, 1, 16, 2000)
+    _say(f"noalloc S_1-row compat ({inst.l},{inst.d}) n={inst.n} m={inst.m}")
+    rc, count, got = _noalloc(inst.seqs, inst.l, inst.d)
+    assert rc == pms.PMS_OK
+    assert got == _existing(inst)
+    assert inst.motif in got
+
+
 def test_noalloc_limits_and_errors():
     _say("noalloc limits")
     lib = _lib()
     assert lib.pms_noalloc_scratch_bytes() == 256 << 20
-    # larger than the scratch array: refused on the host, nothing enqueued
-    huge = I.random_strings(5, 32, 2000)
+    # larger than the scratch array (8191 windows per string: 512 MiB of
+    # work items alone): refused on the host, nothing enqueued
+    huge = I.random_strings(5, 4, 8200)
     rc, _, _ = _noalloc(huge.seqs, 10, 2, keys_cap=16)
     assert rc == pms.PMS_E_NOMEM
     # invalid arguments are refused on the host
