@@ -15,7 +15,9 @@ rate, the Hd compares per second, the dominant kernel's roofline and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Other workloads: --workload plain (the (13,4)/(15,5) single instances),
-serving (a Poisson stream on the served mix), large ((17,6) and (19,7)).
+serving (a Poisson stream on the served mix), large ((17,6) and (19,7)),
+protein (the batched configuration over the 20 amino acids: (l,d) uniform
+from {(11,4),(13,5),(15,6)}, same n and m ranges, seeds 3000-3255).
 """
 from __future__ import annotations
 
@@ -37,6 +39,7 @@ METRIC = "instances/s and Hd compares/s (mixed l,d), batched vs plain GPU, exact
 # instruction is 64 lane-ops issued over 4 cycles on one SIMD)
 PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
 BATCH_SEED0, BATCH_COUNT = 1000, 256
+PROTEIN_SEED0, PROTEIN_LD = 3000, ((11, 4), (13, 5), (15, 6))
 SERVE_LD = ((9, 2), (11, 3), (13, 4), (15, 5), (17, 6))
 
 
@@ -124,11 +127,12 @@ def cpu_baseline(insts, budget_s: float = 20.0):
     for k in sample:
         x = insts[k]
         r = x.m - x.l + 1
-        t = default_threshold(x.n, x.m, x.l, x.d)
+        t = default_threshold(x.n, x.m, x.l, x.d, len(x.alphabet))
         lo, hi, spent, done = 0, 1, 0.0, 0
         while True:
             t0 = time.perf_counter()
-            oracle.solve_b(x.seqs, x.l, x.d, t=t, threads=cores, windows=(lo, hi))
+            oracle.solve_b(x.seqs, x.l, x.d, alphabet=x.alphabet, t=t, threads=cores,
+                           windows=(lo, hi))
             spent += time.perf_counter() - t0
             done += hi - lo
             if hi >= r or spent > per * 0.5:
@@ -157,9 +161,10 @@ def hd_compares(insts, units, t_of):
     return compat, verify
 
 
-def run_batched(args, I, pms):
-    insts = I.batch_mix(BATCH_SEED0, args.count)
-    probs = [pms.Problem(x.seqs, x.l, x.d) for x in insts]
+def run_batched(args, I, pms, insts=None):
+    if insts is None:
+        insts = I.batch_mix(BATCH_SEED0, args.count)
+    probs = [pms.Problem(x.seqs, x.l, x.d, x.alphabet) for x in insts]
     tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc, split=args.split,
                     stage_cap=args.stage_cap)
     default_rate = None
@@ -289,6 +294,32 @@ def batched_main(args, I, pms):
         "max_motifs_per_instance": max(sizes),
         "roofline": roofline,
     }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def protein_main(args, I, pms):
+    """The batched configuration over the 20 amino acids (five-plane l-mers,
+    5-bit keys): batched and plain rates and the CPU oracle beside them."""
+    insts = I.batch_mix(PROTEIN_SEED0, args.count, ld=PROTEIN_LD, alphabet=I.PROTEIN)
+    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate = run_batched(
+        args, I, pms, insts)
+    n = len(insts)
+    value = n * args.steps / elapsed
+    out = {"workload": f"protein batched: {n} planted instances over the 20 amino acids, (l,d) "
+                       "uniform from {(11,4),(13,5),(15,6)}, n in [10,30], m in [300,1000], "
+                       f"seeds {PROTEIN_SEED0}-{PROTEIN_SEED0 + n - 1}; inputs resident in HBM",
+           "instances_per_s": round(value, 3), "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+           "steps": args.steps,
+           "tune": pms.tune_dict(tune),
+           "default_tune_instances_per_s": round(default_rate, 3) if default_rate else None,
+           "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
+           "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
+           "graph_instances_per_s": round(graph_rate, 3) if graph_rate else None,
+           "phases_ms": {k: round(sum(p[i] for p in phases) / len(phases), 3)
+                         for i, k in enumerate(("pack", "compat", "expand", "search", "sort"))},
+           "max_motifs_per_instance": max(sizes)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -453,7 +484,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "plain", "serving", "large"],
+    ap.add_argument("--workload", choices=["batched", "plain", "serving", "large", "protein"],
                     default="batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -482,7 +513,7 @@ def main():
     from paper_1307_0571_amd import instances as I
     from paper_1307_0571_amd import pms
     {"batched": batched_main, "plain": plain_main, "serving": serving_main,
-     "large": large_main}[args.workload](args, I, pms)
+     "large": large_main, "protein": protein_main}[args.workload](args, I, pms)
 
 
 if __name__ == "__main__":

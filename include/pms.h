@@ -8,7 +8,7 @@
  * The result is a set; this library returns it sorted byte-lexicographically
  * with no repeats.
  *
- * Every call below runs the whole method on the GPU: 2-bit l-mer packing,
+ * Every call below runs the whole method on the GPU: planar l-mer packing,
  * the all-pairs Hd <= 2d compatibility bit-matrix (Section 2.1), the
  * sample-driven search over one l-mer per string with per-string survivor
  * filtering by the pair condition and Theorem 1 (Section 2, Section 2.4,
@@ -18,11 +18,15 @@
  * Conventions
  *  - Every function returns PMS_OK (0) or a negative pms_status.
  *  - Strings are NUL-terminated and must have exactly m characters.
- *  - The alphabet must have exactly 4 distinct characters on the GPU path
- *    (DNA: "ACGT"); characters are case-sensitive.  Codes are assigned in
+ *  - The alphabet has 2 to 32 distinct characters (DNA "ACGT", the 20 amino
+ *    acids, ...); characters are case-sensitive.  Codes are assigned in
  *    ascending ASCII order, so the result order is byte order of the motifs.
- *  - Limits of the GPU path: 1 <= l <= 64, 0 <= d < l, 1 <= n <= 32,
- *    m - l + 1 <= 8192.  m < l is valid and yields the empty set.
+ *  - Limits of the GPU path: 0 <= d < l, 1 <= n <= 32, m - l + 1 <= 8192;
+ *    l <= 64 over alphabets of up to 4 letters, l <= 32 over 5 to 16
+ *    letters and l <= 24 over 17 to 32 (two key words of B-bit codes, see
+ *    pms_result).  One batch holds either instances with l > 32 or
+ *    instances over more than 4 letters, not both.  m < l is valid and
+ *    yields the empty set.
  *  - Inputs are caller-owned and read only during the call (create/submit
  *    copy them).  Results are library-allocated host memory released with
  *    pms_result_free().  A hip_stream argument is borrowed (NULL = the
@@ -45,7 +49,7 @@ typedef enum {
     PMS_OK = 0,
     PMS_E_INVAL = -1,       /* bad n, m, l, d, count, NULL pointer or string length */
     PMS_E_ALPHABET = -2,    /* character outside the alphabet, or repeated alphabet character */
-    PMS_E_UNSUPPORTED = -3, /* outside the GPU path's limits (|alphabet| != 4, l > 64, n > 32, ...) */
+    PMS_E_UNSUPPORTED = -3, /* outside the GPU path's limits (|alphabet| > 32, l > 64, n > 32, ...) */
     PMS_E_NOMEM = -4,       /* host or device allocation failed, or above the admission cap */
     PMS_E_DEVICE = -5,      /* a HIP runtime error */
     PMS_E_AGAIN = -6,       /* stream ticket not finished yet */
@@ -68,10 +72,13 @@ typedef struct pms_instance {
 typedef struct {
     int64_t count;     /* number of motifs */
     int32_t l;         /* motif length */
-    int32_t words;     /* 64-bit words per packed key (1 if l <= 32, else 2) */
+    int32_t words;     /* 64-bit words per packed key: ceil(l / floor(64 / B)) */
     char* motifs;      /* count*l characters, no separators, sorted, unique */
-    uint64_t* packed;  /* count*words keys: 2-bit codes, first character in the
-                          most significant bits (left-aligned), same order */
+    uint64_t* packed;  /* count*words keys: B-bit codes (B = 2 for alphabets
+                          of up to 4 letters, else ceil(log2 letters)),
+                          floor(64 / B) characters per word, first character
+                          in the most significant bits (left-aligned), same
+                          order */
 } pms_result;
 
 /* Search parameters.  Zero / negative fields mean "choose automatically".
@@ -81,8 +88,11 @@ typedef struct pms_tune {
     int32_t threshold;      /* stack size t at which the search switches to
                                neighbourhood generation (Section 2.2,
                                Appendix D); 2..8, 0 = cost model */
-    int32_t lmer_words;     /* 1: l-mers in 2 x 32-bit planes (l <= 32);
-                               2: 2 x 64-bit planes ("128-bit"); 0 = 1 if l<=32 */
+    int32_t lmer_words;     /* alphabets of up to 4 letters: 1: l-mers in
+                               2 x 32-bit planes (l <= 32); 2: 2 x 64-bit
+                               planes ("128-bit"); 0 = 1 if l<=32.  A batch
+                               with a larger alphabet always uses 5 x 32-bit
+                               planes */
     int32_t triple_filter;  /* >= 0: filter survivors with Theorem 1 (default),
                                < 0: pairwise 2d filter only */
     int32_t waves_per_cu;   /* resident search waves per CU (persistent grid); 0 = auto */
@@ -265,12 +275,15 @@ int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t m, const c
 size_t pms_noalloc_scratch_bytes(void);
 
 /* Appendix D cost-model threshold the library uses when tune.threshold is 0
- * (a stack size in [2, 8]); host-only. */
-int pms_default_threshold(int n, int m, int l, int d);
-/* Appendix C expected number of motifs of a random DNA instance (n strings
- * of length m, i.i.d. uniform bases): 4^l (1 - (1 - N_d / 4^l)^(m-l+1))^n;
- * host-only.  Sizes the output slots when tune.out_capacity is 0. */
-double pms_expected_motifs(int n, int m, int l, int d);
+ * (a stack size in [2, 8]) for an alphabet of sigma letters (sigma < 2 is
+ * taken as 4); host-only. */
+int pms_default_threshold(int n, int m, int l, int d, int sigma);
+/* Appendix C expected number of motifs of a random instance (n strings of
+ * length m, i.i.d. uniform letters of an alphabet of sigma, sigma < 2 taken
+ * as 4): sigma^l (1 - (1 - N_d / sigma^l)^(m-l+1))^n with
+ * N_d = sum_{i<=d} C(l,i) (sigma-1)^i; host-only.  Sizes the output slots
+ * when tune.out_capacity is 0. */
+double pms_expected_motifs(int n, int m, int l, int d, int sigma);
 
 /* Number of visible GPUs (0 when none; never an error for "no device"). */
 int pms_device_count(int32_t* count);

@@ -12,7 +12,9 @@ namespace pms {
 // Limits of the device path.
 constexpr int kMaxN = 32;        // strings per instance (row bit masks are 32-bit)
 constexpr int kMaxR = 8192;      // windows per string (13-bit window index)
-constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes)
+constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes; alphabets of up to 4 letters)
+constexpr int kMaxLWide = 32;    // motif length over larger alphabets (five 32-bit planes)
+constexpr int kMaxAlpha = 32;    // letters (5-bit codes)
 constexpr int kMaxT = 8;         // stack size at which generation starts
 constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
 constexpr int kStageCapMin = 512;   // staged survivors of one tail batch (LDS entries)
@@ -43,6 +45,9 @@ struct InstDev {
     int32_t triple;   // Theorem 1 survivor filter on/off
     int32_t s1_lo, s1_hi;  // S_1 windows searched: [s1_lo, s1_hi)
     int32_t c1only;   // compat rows only for the l-mers of S_1; pushes test Hd <= 2d directly
+    int32_t asize;    // letters of the alphabet (codes 0 .. asize-1)
+    int32_t abits;    // key bits per character (2 up to 4 letters, else ceil(log2 asize))
+    uint32_t amask;   // (1 << asize) - 1: every child of a generator node
     int32_t pad;
     int64_t chars_off;   // byte offset of the n*m characters
     int64_t lmer_off;    // l-mer offset (units of one packed l-mer)
@@ -96,7 +101,8 @@ struct LaunchPlan {
     int max_n;
     int level_words;     // max over instances of n*bw (u64 words per search level)
     int tmax;            // max threshold in the batch (template selector)
-    int words;           // l-mer width (1 or 2)
+    int words;           // l-mer class: 1, 2 (two 32- / 64-bit planes), 3 (five 32-bit planes)
+    int kwords;          // u64 words per motif key (1 or 2)
     int search_blocks;   // persistent grid size
     int compat_kernel;   // 1 VALU
     int split;           // survivors of one string a wave keeps (the rest: split items)
@@ -129,10 +135,11 @@ hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
 hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 size_t search_lds_bytes(const LaunchPlan& p);
+size_t lmer_bytes(int words);
 
 // Memory plan bounds (pms_runtime.cpp): a batch needs at most
 // fixed_bytes(tune) + the sum of inst_bytes(...) over its instances.
-size_t inst_bytes(int n, int m, int l, int d, const ::pms_tune* tune);
+size_t inst_bytes(int n, int m, int l, int d, int sigma, const ::pms_tune* tune);
 size_t fixed_bytes(const ::pms_tune* tune);
 
 // The autotuner's cached setting for a batch of this shape (pms_tune.cpp).

@@ -2,16 +2,22 @@
 //
 // Data layout (per instance, all in HBM):
 //   chars   n*m bytes, row-major (string i at i*m)
-//   lmers   N = n*r packed l-mers, id g = row*r + window.  Planar 2-bit
-//           packing: bit p of plane h / lo is the high / low bit of the code
-//           of character p, so Hd(u,v) = popcount((u.h^v.h) | (u.lo^v.lo)).
-//           W = 1: two 32-bit planes (l <= 32); W = 2: two 64-bit planes.
+//   lmers   N = n*r packed l-mers, id g = row*r + window.  Planar packing
+//           (Section 2.1 stores l * ceil(log2 |alphabet|) bits per l-mer):
+//           bit p of plane b is bit b of the code of character p, so
+//           Hd(u,v) = popcount of the OR over the planes of u XOR v.
+//           W = 1: two 32-bit planes (alphabets of up to 4 letters, l <= 32);
+//           W = 2: two 64-bit planes (up to 4 letters, l <= 64); W = 3: five
+//           32-bit planes (up to 32 letters, such as the 20 amino acids,
+//           l <= 32).
 //   compat  [N][n][bw] u64 bitsets: bit x of word (u, j, x/64) is set iff
 //           Hd(u, window x of string j) <= 2d and u is not in string j
 //           (the pair condition of Section 2.4, precomputed as Section 2.1
 //           describes).
-//   keys    motif keys, 2 bits per character, first character in the most
-//           significant bits; W words per key.
+//   keys    motif keys, B bits per character (B = 2 up to 4 letters, else
+//           ceil(log2 |alphabet|)), floor(64 / B) characters per word, first
+//           character in the most significant bits; KW words per key (1 for
+//           W = 1, else 2).
 //
 // Pipeline: pack -> compat -> expand (level 1, one wave per S_1 window;
 // pushes level-2 work items to a device queue) -> search (persistent waves
@@ -28,14 +34,37 @@ namespace pms {
 template <int W> struct Lm;
 template <> struct Lm<1> { uint32_t h, lo; };
 template <> struct Lm<2> { uint64_t h, lo; };
+// larger alphabets: plane lo holds bit 0 of every character's code, h bit 1,
+// x2 .. x4 bits 2 .. 4
+template <> struct Lm<3> { uint32_t h, lo, x2, x3, x4; };
 template <int W> struct MaskOf { typedef uint64_t type; };
 template <> struct MaskOf<1> { typedef uint32_t type; };
+template <> struct MaskOf<3> { typedef uint32_t type; };
+template <int W> struct KeyWords { static constexpr int value = W == 1 ? 1 : 2; };
 
 __device__ __forceinline__ uint32_t dmask(const Lm<1>& a, const Lm<1>& b) {
     return (a.h ^ b.h) | (a.lo ^ b.lo);
 }
 __device__ __forceinline__ uint64_t dmask(const Lm<2>& a, const Lm<2>& b) {
     return (a.h ^ b.h) | (a.lo ^ b.lo);
+}
+__device__ __forceinline__ uint32_t dmask(const Lm<3>& a, const Lm<3>& b) {
+    return (a.h ^ b.h) | (a.lo ^ b.lo) | (a.x2 ^ b.x2) | (a.x3 ^ b.x3) | (a.x4 ^ b.x4);
+}
+template <int W> __device__ __forceinline__ Lm<W> lm_zero() {
+    Lm<W> v{};
+    return v;
+}
+// code of character p
+__device__ __forceinline__ uint32_t code_at(const Lm<1>& v, int p) {
+    return ((v.h >> p) & 1u) << 1 | ((v.lo >> p) & 1u);
+}
+__device__ __forceinline__ uint32_t code_at(const Lm<2>& v, int p) {
+    return (uint32_t)(((v.h >> p) & 1ull) << 1 | ((v.lo >> p) & 1ull));
+}
+__device__ __forceinline__ uint32_t code_at(const Lm<3>& v, int p) {
+    return ((v.x4 >> p) & 1u) << 4 | ((v.x3 >> p) & 1u) << 3 | ((v.x2 >> p) & 1u) << 2 |
+           ((v.h >> p) & 1u) << 1 | ((v.lo >> p) & 1u);
 }
 __device__ __forceinline__ int pc(uint32_t x) { return __popc(x); }
 __device__ __forceinline__ int pc(uint64_t x) { return __popcll(x); }
@@ -123,18 +152,28 @@ __global__ __launch_bounds__(256) void k_pack(const InstDev* __restrict__ insts,
     const int row = g / I.r, w = g - row * I.r;
     const uint8_t* p = chars + I.chars_off + (int64_t)row * I.m + w;
     const uint8_t* tab = lut + (int64_t)blockIdx.y * 256;
-    M h = 0, lo = 0;
+    M h = 0, lo = 0, x2 = 0, x3 = 0, x4 = 0;
     bool bad = false;
     for (int i = 0; i < I.l; i++) {
         uint32_t c = tab[p[i]];
         bad |= c == 0xFFu;
         h |= (M)((c >> 1) & 1u) << i;
         lo |= (M)(c & 1u) << i;
+        if constexpr (W == 3) {
+            x2 |= (M)((c >> 2) & 1u) << i;
+            x3 |= (M)((c >> 3) & 1u) << i;
+            x4 |= (M)((c >> 4) & 1u) << i;
+        }
     }
     if (bad) atomicOr(&ctr[blockIdx.y].flags, kFlagBadChar);
-    Lm<W> v;
+    Lm<W> v = lm_zero<W>();
     v.h = h;
     v.lo = lo;
+    if constexpr (W == 3) {
+        v.x2 = x2;
+        v.x3 = x3;
+        v.x4 = x4;
+    }
     lmers[I.lmer_off + g] = v;
 }
 
@@ -168,8 +207,7 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
             u[k] = L[g];
             urow[k] = g / I.r;
         } else {
-            u[k].h = 0;
-            u[k].lo = 0;
+            u[k] = lm_zero<W>();
             urow[k] = -1;
         }
     }
@@ -178,12 +216,7 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
     for (int w = 0; w < I.bw; w++) {
         const int x = w * 64 + lane;
         const bool valid = x < I.r;
-        Lm<W> v;
-        if (valid) v = L[j * I.r + x];
-        else {
-            v.h = 0;
-            v.lo = 0;
-        }
+        const Lm<W> v = valid ? L[j * I.r + x] : lm_zero<W>();
 #pragma unroll
         for (int k = 0; k < kCompatTile; k++) {
             if (urow[k] < 0) continue;
@@ -317,8 +350,8 @@ struct SearchLds {
     int item;
     int xs[kTailSlots];              // window of each slot's candidate
     int aslot[kTailSlots];           // live slots, in order
-    typename MaskOf<W>::type dq_h[64], dq_l[64];  // donated subtrees: prefix planes,
-    uint8_t dq_d[64], dq_s[64];                   // depth and slot
+    Lm<W> dq_v[64];                  // donated subtrees: prefix,
+    uint8_t dq_d[64], dq_s[64];      // depth and slot
 };
 
 template <int W>
@@ -336,13 +369,30 @@ __device__ __forceinline__ uint64_t key_word(uint64_t h, uint64_t lo, int from, 
 __device__ __forceinline__ uint32_t low_bits(uint32_t, int s) { return s >= 32 ? ~0u : ((1u << s) - 1u); }
 __device__ __forceinline__ uint64_t low_bits(uint64_t, int s) { return s >= 64 ? ~0ull : ((1ull << s) - 1ull); }
 
-// 4-bit child mask from a pair's or triple's slack: child c is kept when
-// slack >= (members) - (members whose character at the position is c).
-__device__ __forceinline__ uint32_t slack2(int s, uint32_t oa, uint32_t ob) {
-    return s >= 2 ? 0xFu : s == 1 ? (oa | ob) : s == 0 ? (oa & ob) : 0u;
+// Prefix v with character ch at position q (positions after q cleared).
+template <int W>
+__device__ __forceinline__ Lm<W> with_char(const Lm<W>& v, int q, uint32_t ch) {
+    typedef typename MaskOf<W>::type M;
+    const M keep = low_bits((M)0, q);
+    Lm<W> o = lm_zero<W>();
+    o.h = (M)((v.h & keep) | ((M)((ch >> 1) & 1u) << q));
+    o.lo = (M)((v.lo & keep) | ((M)(ch & 1u) << q));
+    if constexpr (W == 3) {
+        o.x2 = (v.x2 & keep) | (((ch >> 2) & 1u) << q);
+        o.x3 = (v.x3 & keep) | (((ch >> 3) & 1u) << q);
+        o.x4 = (v.x4 & keep) | (((ch >> 4) & 1u) << q);
+    }
+    return o;
 }
-__device__ __forceinline__ uint32_t slack3(int s, uint32_t oa, uint32_t ob, uint32_t oc) {
-    return s >= 3 ? 0xFu
+
+// Child mask (bit c: character code c; `full` = every letter of the
+// alphabet) from a pair's or triple's slack: child c is kept when
+// slack >= (members) - (members whose character at the position is c).
+__device__ __forceinline__ uint32_t slack2(int s, uint32_t oa, uint32_t ob, uint32_t full) {
+    return s >= 2 ? full : s == 1 ? (oa | ob) : s == 0 ? (oa & ob) : 0u;
+}
+__device__ __forceinline__ uint32_t slack3(int s, uint32_t oa, uint32_t ob, uint32_t oc, uint32_t full) {
+    return s >= 3 ? full
          : s == 2 ? (oa | ob | oc)
          : s == 1 ? ((oa & ob) | (oa & oc) | (ob & oc))
          : s == 0 ? (oa & ob & oc) : 0u;
@@ -351,7 +401,9 @@ __device__ __forceinline__ uint32_t slack3(int s, uint32_t oa, uint32_t ob, uint
 template <int W, int TMAX>
 struct Searcher {
     typedef typename MaskOf<W>::type M;
-    static constexpr int NW = W == 1 ? 2 : 4;  // u64 words of child nibbles (16 depths each)
+    // u64 words of child nibbles (16 depths each; alphabets of up to 4
+    // letters); larger alphabets keep one 32-bit child mask per depth in LDS
+    static constexpr int NW = W == 1 ? 2 : W == 2 ? 4 : 1;
     SearchLds<W, TMAX>& S;
     uint64_t* lv;  // LDS level bitsets: level k at lv + (k - 2) * level_words
     int level_words;
@@ -373,6 +425,7 @@ struct Searcher {
     int s2cap, mw;        // staging area (entries of sizeof(Lm<W>)), survivor-bit words per slot
     bool half;            // W == 1 and l <= 16: staged l-mers packed in 4 bytes
     int scap;             // staged l-mers that fit
+    uint32_t* cm;         // W == 3: [32 depths][64 lanes] child masks
 
     __device__ __forceinline__ uint64_t* level(int k) { return lv + (k - 2) * level_words; }
     __device__ __forceinline__ unsigned& cnt_word(int k, int j) { return cntw[k * kMaxN + j]; }
@@ -477,8 +530,7 @@ struct Searcher {
                     for (int u = 0; u < 4; u++) {
                         const int q = q0 + 64 * u + lane;
                         e[u] = -1;
-                        v[u].h = 0;
-                        v[u].lo = 0;
+                        v[u] = lm_zero<W>();
                         if (q < cnt) {
                             e[u] = (int)s2[q].lo;
                             v[u] = L[(int)s2[q].h];
@@ -574,10 +626,29 @@ struct Searcher {
         if (!ok) return;
         const unsigned long long at = base + (unsigned long long)rank_below(em);
         if (at < (unsigned long long)I.out_cap) {
-            const uint64_t h = (uint64_t)mv.h, lo = (uint64_t)mv.lo;
-            uint64_t* dst = keys + (I.out_off + (int64_t)at) * W;
-            dst[0] = key_word<W>(h, lo, 0, I.l < 32 ? I.l : 32);
-            if (W == 2) dst[1] = I.l > 32 ? key_word<W>(h, lo, 32, I.l) : 0ull;
+            constexpr int KW = KeyWords<W>::value;
+            uint64_t* dst = keys + (I.out_off + (int64_t)at) * KW;
+            if constexpr (W == 3) {
+                // I.abits bits per character, floor(64 / I.abits) per word
+                uint64_t k[2] = {0ull, 0ull};
+                int wq = 0, sh = 64;
+                for (int p = 0; p < I.l; p++) {
+                    if (sh < I.abits) {
+                        wq = 1;
+                        sh = 64;
+                    }
+                    sh -= I.abits;
+                    const uint64_t c = code_at(mv, p);
+                    if (wq == 0) k[0] |= c << sh;
+                    else k[1] |= c << sh;
+                }
+                dst[0] = k[0];
+                dst[1] = k[1];
+            } else {
+                const uint64_t h = (uint64_t)mv.h, lo = (uint64_t)mv.lo;
+                dst[0] = key_word<W>(h, lo, 0, I.l < 32 ? I.l : 32);
+                if (W == 2) dst[1] = I.l > 32 ? key_word<W>(h, lo, 32, I.l) : 0ull;
+            }
         } else {
             atomicOr(&ctr[inst].flags, kFlagOutOverflow);
         }
@@ -589,7 +660,7 @@ struct Searcher {
     __device__ __forceinline__ Lm<W> s2get(int i) const {
         if (W == 1 && half) {
             const uint32_t v = s2h()[i];
-            Lm<W> x;
+            Lm<W> x = lm_zero<W>();
             x.h = (M)(v & 0xFFFFu);
             x.lo = (M)(v >> 16);
             return x;
@@ -768,25 +839,25 @@ struct Searcher {
     // Valid children (4-bit mask) of the node at depth P whose prefix is mv
     // (characters 0..P-1), for members mh/ml[0..K) with pair masks e2:
     // Algorithm 1's prune with budgets d - Hd(prefix) and suffixes from P+1.
-    __device__ __forceinline__ uint32_t expand(const M (&mh)[TMAX], const M (&ml)[TMAX],
-                                               const M (&e2)[TMAX][TMAX], int K, M vh, M vl,
-                                               int P) const {
+    __device__ __forceinline__ uint32_t expand(const Lm<W> (&mm)[TMAX], const M (&e2)[TMAX][TMAX],
+                                               int K, const Lm<W>& v, int P) const {
         const M below = low_bits((M)0, P);
         const int d = I.d;
+        // every letter: codes 0..3 in the two-plane class (a smaller
+        // alphabet's codes are masked once at the end), I.amask otherwise
+        const uint32_t full = W == 3 ? I.amask : 0xFu;
         int rb[TMAX];
         uint32_t oh[TMAX];
-        uint32_t allowed = 0xFu;
+        uint32_t allowed = full;
 #pragma unroll
         for (int a = 0; a < TMAX; a++) {
             if (a < K) {
-                rb[a] = d - pc((M)(((vh ^ mh[a]) | (vl ^ ml[a])) & below));
-                const uint32_t ca = (uint32_t)((((uint64_t)mh[a] >> P) & 1ull) << 1 |
-                                               (((uint64_t)ml[a] >> P) & 1ull));
-                oh[a] = 1u << ca;
-                allowed &= rb[a] >= 1 ? 0xFu : rb[a] == 0 ? oh[a] : 0u;
+                rb[a] = d - pc((M)(dmask(v, mm[a]) & below));
+                oh[a] = 1u << code_at(mm[a], P);
+                allowed &= rb[a] >= 1 ? full : rb[a] == 0 ? oh[a] : 0u;
             } else {
                 rb[a] = 0;
-                oh[a] = 0xFu;
+                oh[a] = full;
             }
         }
         const int sfx = P + 1;
@@ -794,7 +865,7 @@ struct Searcher {
         for (int a = 0; a < TMAX; a++)
 #pragma unroll
             for (int b = a + 1; b < TMAX; b++)
-                if (b < K) allowed &= slack2(rb[a] + rb[b] - pc(suf(e2[a][b], sfx)), oh[a], oh[b]);
+                if (b < K) allowed &= slack2(rb[a] + rb[b] - pc(suf(e2[a][b], sfx)), oh[a], oh[b], full);
 #pragma unroll
         for (int a = 0; a < TMAX; a++)
 #pragma unroll
@@ -805,9 +876,9 @@ struct Searcher {
                         const M u = (M)(e2[a][b] | e2[a][c]);
                         const M x = (M)(e2[a][b] & e2[a][c] & e2[b][c]);
                         const int cd = pc(suf(u, sfx)) + pc(suf(x, sfx));
-                        allowed &= slack3(rb[a] + rb[b] + rb[c] - cd, oh[a], oh[b], oh[c]);
+                        allowed &= slack3(rb[a] + rb[b] + rb[c] - cd, oh[a], oh[b], oh[c], full);
                     }
-        return allowed;
+        return W == 3 ? allowed : allowed & I.amask;
     }
 
     // Whether the node at depth P with prefix mv is in the pruned tree
@@ -815,15 +886,14 @@ struct Searcher {
     // valid node's ancestors are valid too (each condition only loosens
     // towards the root), so the valid nodes of one depth split the tree's
     // leaves into disjoint subtrees.
-    __device__ __forceinline__ bool node_valid(const M (&mh)[TMAX], const M (&ml)[TMAX],
-                                               const M (&e2)[TMAX][TMAX], int K, M vh, M vl,
-                                               int P) const {
+    __device__ __forceinline__ bool node_valid(const Lm<W> (&mm)[TMAX], const M (&e2)[TMAX][TMAX],
+                                               int K, const Lm<W>& v, int P) const {
         const M below = low_bits((M)0, P);
         int rb[TMAX];
         bool ok = true;
 #pragma unroll
         for (int a = 0; a < TMAX; a++) {
-            rb[a] = a < K ? I.d - pc((M)(((vh ^ mh[a]) | (vl ^ ml[a])) & below)) : 0;
+            rb[a] = a < K ? I.d - pc((M)(dmask(v, mm[a]) & below)) : 0;
             ok &= rb[a] >= 0;
         }
 #pragma unroll
@@ -866,9 +936,7 @@ struct Searcher {
             for (int c0 = 0; c0 < nl; c0 += 64) {
                 const int i = c0 + lane;
                 const bool act = i < nl;
-                Lm<W> mv;
-                mv.h = 0;
-                mv.lo = 0;
+                Lm<W> mv = lm_zero<W>();
                 int sl = 0;
                 if (act) {
                     mv = leaf[i];
@@ -930,9 +998,7 @@ struct Searcher {
         }
         for (int c0 = 0; c0 < nl; c0 += 64) {
             const int i = c0 + lane;
-            Lm<W> mv;
-            mv.h = 0;
-            mv.lo = 0;
+            Lm<W> mv = lm_zero<W>();
             const bool ok = i < nl;
             if (ok) mv = leaf[i];
             emit(mv, ok);
@@ -942,36 +1008,67 @@ struct Searcher {
 
     // Member K-1 is the slot's candidate (compile-time indices only: K is
     // uniform but not a constant).
-    __device__ __forceinline__ void load_slot(M (&mh)[TMAX], M (&ml)[TMAX], M (&e2)[TMAX][TMAX],
-                                              int K, int sl) const {
+    __device__ __forceinline__ void load_slot(Lm<W> (&mm)[TMAX], M (&e2)[TMAX][TMAX], int K,
+                                              int sl) const {
         const Lm<W> c = ut[sl];
 #pragma unroll
         for (int a = 0; a < TMAX; a++)
-            if (a == K - 1) {
-                mh[a] = (M)c.h;
-                ml[a] = (M)c.lo;
-            }
+            if (a == K - 1) mm[a] = c;
 #pragma unroll
         for (int a = 0; a < TMAX; a++)
 #pragma unroll
             for (int b = a + 1; b < TMAX; b++)
-                if (b == K - 1) e2[a][b] = (M)((mh[a] ^ (M)c.h) | (ml[a] ^ (M)c.lo));
+                if (b == K - 1) e2[a][b] = (M)dmask(mm[a], c);
+    }
+
+    // Unvisited children of depth q on a lane's path: 4-bit nibbles in
+    // registers (alphabets of up to 4 letters) or a 32-bit mask in LDS.
+    __device__ __forceinline__ uint32_t kids_get(const uint64_t (&av)[NW], int q) const {
+        if constexpr (W == 3) {
+            return cm[q * 64 + lane];
+        } else {
+            uint32_t nib = 0;
+#pragma unroll
+            for (int i = 0; i < NW; i++)
+                if (i == (q >> 4)) nib = (uint32_t)(av[i] >> (4 * (q & 15))) & 0xFu;
+            return nib;
+        }
+    }
+    __device__ __forceinline__ void kids_put(uint64_t (&av)[NW], int q, uint32_t m) const {
+        if constexpr (W == 3) {
+            cm[q * 64 + lane] = m;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; i++)
+                if (i == (q >> 4)) {
+                    const int sh = 4 * (q & 15);
+                    av[i] = (av[i] & ~(0xFull << sh)) | ((uint64_t)m << sh);
+                }
+        }
+    }
+    // depth q's entry is empty (every deeper depth is exhausted first)
+    __device__ __forceinline__ void kids_fresh(uint64_t (&av)[NW], int q, uint32_t m) const {
+        if constexpr (W == 3) {
+            cm[q * 64 + lane] = m;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; i++)
+                if (i == (q >> 4)) av[i] |= (uint64_t)m << (4 * (q & 15));
+        }
     }
 
     // Start a walk at the valid node (vh, vl) of depth P: its child nibble,
     // or a leaf when P == l (returned).
-    __device__ __forceinline__ bool start(const M (&mh)[TMAX], const M (&ml)[TMAX],
-                                          const M (&e2)[TMAX][TMAX], int K, M vh, M vl, int P,
-                                          uint64_t (&av)[NW], uint64_t& nz, bool& has) const {
+    __device__ __forceinline__ bool start(const Lm<W> (&mm)[TMAX], const M (&e2)[TMAX][TMAX],
+                                          int K, const Lm<W>& v, int P, uint64_t (&av)[NW],
+                                          uint64_t& nz, bool& has) const {
 #pragma unroll
         for (int i = 0; i < NW; i++) av[i] = 0ull;
         nz = 0;
         if (P == I.l) return true;
-        const uint32_t nb = expand(mh, ml, e2, K, vh, vl, P);
+        const uint32_t nb = expand(mm, e2, K, v, P);
         if (nb) {
-#pragma unroll
-            for (int i = 0; i < NW; i++)
-                if (i == (P >> 4)) av[i] = (uint64_t)nb << (4 * (P & 15));
+            kids_fresh(av, P, nb);
             nz = 1ull << P;
             has = true;
         }
@@ -995,23 +1092,28 @@ struct Searcher {
         }
         __syncthreads();
         // shared members and their pair masks (uniform)
-        M mh[TMAX], ml[TMAX], e2[TMAX][TMAX];
+        Lm<W> mm[TMAX];
+        M e2[TMAX][TMAX];
 #pragma unroll
         for (int a = 0; a < TMAX; a++) {
             const int aa = a < K - 1 ? a : 0;
-            mh[a] = (M)S.st[aa].h;
-            ml[a] = (M)S.st[aa].lo;
+            mm[a] = S.st[aa];
 #pragma unroll
             for (int b = 0; b < TMAX; b++) e2[a][b] = (a < b && b < K - 1) ? (M)S.E[a][b] : (M)0;
         }
-        int D = nalive >= 4 ? 2 : 3;
+        // first subtrees: every prefix of D characters of every live slot
+        // (alphabets of up to 4 letters: D = 2 or 3, base-4 digits; larger
+        // alphabets: D = 1)
+        const int A = I.asize;
+        int D = W == 3 ? 1 : nalive >= 4 ? 2 : 3;
         if (D > l) D = l;
-        const int units = nalive << (2 * D);
+        const int per = W == 3 ? A : 1 << (2 * D);
+        const int units = nalive * per;
         int next = 0;
         int nl = 0;
         bool has = false;
         int slot = 0;
-        M vh = 0, vl = 0;
+        Lm<W> v = lm_zero<W>();
         uint64_t av[NW];
 #pragma unroll
         for (int i = 0; i < NW; i++) av[i] = 0ull;
@@ -1031,18 +1133,23 @@ struct Searcher {
                     if (!has) {
                         const int u = next + rank_below(need);
                         if (u < units) {
-                            slot = S.aslot[u >> (2 * D)];
-                            load_slot(mh, ml, e2, K, slot);
-                            const int pre = u & ((1 << (2 * D)) - 1);
-                            vh = 0;
-                            vl = 0;
-                            for (int q = 0; q < D; q++) {
-                                const int ch = (pre >> (2 * (D - 1 - q))) & 3;
-                                vh |= (M)(ch >> 1) << q;
-                                vl |= (M)(ch & 1) << q;
+                            const int su = W == 3 ? u / A : u >> (2 * D);
+                            slot = S.aslot[su];
+                            load_slot(mm, e2, K, slot);
+                            const int pre = u - su * per;
+                            v = lm_zero<W>();
+                            bool in_alpha = true;
+                            if constexpr (W == 3) {
+                                v = with_char<W>(v, 0, (uint32_t)pre);
+                            } else {
+                                for (int q = 0; q < D; q++) {
+                                    const int ch = (pre >> (2 * (D - 1 - q))) & 3;
+                                    in_alpha &= ch < A;
+                                    v = with_char<W>(v, q, (uint32_t)ch);
+                                }
                             }
-                            if (node_valid(mh, ml, e2, K, vh, vl, D))
-                                isleaf = start(mh, ml, e2, K, vh, vl, D, av, nz, has);
+                            if (in_alpha && node_valid(mm, e2, K, v, D))
+                                isleaf = start(mm, e2, K, v, D, av, nz, has);
                         }
                     }
                     next += nidle;
@@ -1055,9 +1162,7 @@ struct Searcher {
                 bool donor = false;
                 if (has) {
                     q0 = __builtin_ctzll(nz);
-#pragma unroll
-                    for (int i = 0; i < NW; i++)
-                        if (i == (q0 >> 4)) nib0 = (uint32_t)(av[i] >> (4 * (q0 & 15))) & 0xFu;
+                    nib0 = kids_get(av, q0);
                     donor = __popcll(nz) >= 2 || __popc(nib0) >= 2;
                 }
                 const unsigned long long dm = ballot(donor);
@@ -1066,17 +1171,10 @@ struct Searcher {
                     if (donor && rank_below(dm) < ndon) {
                         const int ch = __builtin_ctz(nib0);
                         nib0 &= nib0 - 1;
-#pragma unroll
-                        for (int i = 0; i < NW; i++)
-                            if (i == (q0 >> 4)) {
-                                const int sh = 4 * (q0 & 15);
-                                av[i] = (av[i] & ~(0xFull << sh)) | ((uint64_t)nib0 << sh);
-                            }
+                        kids_put(av, q0, nib0);
                         if (!nib0) nz &= ~(1ull << q0);
-                        const M keep = low_bits((M)0, q0);
                         const int at = rank_below(dm);
-                        S.dq_h[at] = (M)((vh & keep) | ((M)(ch >> 1) << q0));
-                        S.dq_l[at] = (M)((vl & keep) | ((M)(ch & 1) << q0));
+                        S.dq_v[at] = with_char<W>(v, q0, (uint32_t)ch);
                         S.dq_d[at] = (uint8_t)(q0 + 1);
                         S.dq_s[at] = (uint8_t)slot;
                     }
@@ -1084,10 +1182,9 @@ struct Searcher {
                     if (!has && rank_below(need) < ndon) {
                         const int at = rank_below(need);
                         slot = S.dq_s[at];
-                        load_slot(mh, ml, e2, K, slot);
-                        vh = S.dq_h[at];
-                        vl = S.dq_l[at];
-                        isleaf = start(mh, ml, e2, K, vh, vl, (int)S.dq_d[at], av, nz, has);
+                        load_slot(mm, e2, K, slot);
+                        v = S.dq_v[at];
+                        isleaf = start(mm, e2, K, v, (int)S.dq_d[at], av, nz, has);
                     }
                     __syncthreads();
                 }
@@ -1095,29 +1192,18 @@ struct Searcher {
             if (has && !isleaf) {
                 // deepest depth with an unvisited child
                 const int q = 63 - __builtin_clzll(nz);
-                const int wq = q >> 4, sh = 4 * (q & 15);
-                uint32_t nib = 0;
-#pragma unroll
-                for (int i = 0; i < NW; i++)
-                    if (i == wq) nib = (uint32_t)(av[i] >> sh) & 0xFu;
+                uint32_t nib = kids_get(av, q);
                 const int ch = __builtin_ctz(nib);
                 nib &= nib - 1;
-#pragma unroll
-                for (int i = 0; i < NW; i++)
-                    if (i == wq) av[i] = (av[i] & ~(0xFull << sh)) | ((uint64_t)nib << sh);
+                kids_put(av, q, nib);
                 if (!nib) nz &= ~(1ull << q);
-                const M keep = low_bits((M)0, q);
-                vh = (M)((vh & keep) | ((M)(ch >> 1) << q));
-                vl = (M)((vl & keep) | ((M)(ch & 1) << q));
+                v = with_char<W>(v, q, (uint32_t)ch);
                 if (q + 1 == l) {
                     isleaf = true;
                 } else {
-                    const uint32_t nb = expand(mh, ml, e2, K, vh, vl, q + 1);
+                    const uint32_t nb = expand(mm, e2, K, v, q + 1);
                     if (nb) {
-                        const int w1 = (q + 1) >> 4, s1 = 4 * ((q + 1) & 15);
-#pragma unroll
-                        for (int i = 0; i < NW; i++)
-                            if (i == w1) av[i] |= (uint64_t)nb << s1;
+                        kids_fresh(av, q + 1, nb);
                         nz |= 1ull << (q + 1);
                     }
                 }
@@ -1126,8 +1212,7 @@ struct Searcher {
             const unsigned long long lm = ballot(isleaf);
             if (isleaf) {
                 const int at = nl + rank_below(lm);
-                leaf[at].h = vh;
-                leaf[at].lo = vl;
+                leaf[at] = v;
                 leafslot[at] = (uint8_t)slot;
             }
             nl += __popcll(lm);
@@ -1224,6 +1309,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
     Lm<W>* ut = reinterpret_cast<Lm<W>*>(memb + kTailSlots * mw);
     Lm<W>* leaf = ut + kTailSlots;
     uint8_t* leafslot = reinterpret_cast<uint8_t*>(leaf + kLeafCap);
+    uint32_t* cm = W == 3 ? reinterpret_cast<uint32_t*>(leafslot + kLeafCap) : nullptr;
     for (;;) {
         if (lane == 0) {
             unsigned long long it = atomicAdd(&q->item_next, 1ull);
@@ -1260,7 +1346,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
                              compat + I.compat_off, (uint64_t)u1, keys, ctr, lane, cntw,
                              I.bw > 1 ? (uint32_t)((0xFFFFFFFFull + (uint64_t)I.bw) / (uint64_t)I.bw) : 0u,
                              s2, memb, ut, leaf, leafslot, s2cap, mw, W == 1 && I.l <= 16,
-                             (W == 1 && I.l <= 16) ? 2 * s2cap : s2cap};
+                             (W == 1 && I.l <= 16) ? 2 * s2cap : s2cap, cm};
         if (lane == 0) {
             S.st[0] = sr.L[u1];
             S.rows[1] = (I.n >= 32 ? 0xFFFFFFFFu : ((1u << I.n) - 1u)) & ~1u;
@@ -1548,9 +1634,12 @@ hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream
     if (p.words == 1)
         hipLaunchKernelGGL(k_pack<1>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
                            (Lm<1>*)b.lmers, b.ctr);
-    else
+    else if (p.words == 2)
         hipLaunchKernelGGL(k_pack<2>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
                            (Lm<2>*)b.lmers, b.ctr);
+    else
+        hipLaunchKernelGGL(k_pack<3>, grid, dim3(256), 0, stream, b.inst, b.chars, b.lut,
+                           (Lm<3>*)b.lmers, b.ctr);
     return hipGetLastError();
 }
 
@@ -1562,8 +1651,11 @@ hipError_t launch_compat(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
     if (p.words == 1)
         hipLaunchKernelGGL(k_compat<1>, grid, dim3(256), 0, stream, b.inst, (const Lm<1>*)b.lmers,
                            b.compat);
-    else
+    else if (p.words == 2)
         hipLaunchKernelGGL(k_compat<2>, grid, dim3(256), 0, stream, b.inst, (const Lm<2>*)b.lmers,
+                           b.compat);
+    else
+        hipLaunchKernelGGL(k_compat<3>, grid, dim3(256), 0, stream, b.inst, (const Lm<3>*)b.lmers,
                            b.compat);
     return hipGetLastError();
 }
@@ -1575,15 +1667,20 @@ hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
     return hipGetLastError();
 }
 
+size_t lmer_bytes(int words) {
+    return words == 1 ? sizeof(Lm<1>) : words == 2 ? sizeof(Lm<2>) : sizeof(Lm<3>);
+}
+
 size_t search_lds_bytes(const LaunchPlan& p) {
-    const size_t lm = p.words == 1 ? sizeof(Lm<1>) : sizeof(Lm<2>);
+    const size_t lm = lmer_bytes(p.words);
     // levels 2 .. max(2, t-1): the last member never gets a level of its own
     // (the tail batch replaces that push)
     const size_t lv = (size_t)(p.tmax > 3 ? p.tmax - 2 : 1) * (size_t)p.level_words * 8u;
     const size_t mw = (size_t)(p.words == 1 ? 2 : 1) * (size_t)(p.s2cap / 64);
     const size_t tail = (size_t)p.s2cap * lm + (size_t)kTailSlots * mw * 8u +
                         (size_t)kTailSlots * lm + (size_t)kLeafCap * lm + (size_t)kLeafCap;
-    return lv + tail;
+    const size_t kids = p.words == 3 ? (size_t)32 * 64 * 4 : 0;  // child masks per depth and lane
+    return lv + tail + kids;
 }
 
 template <int W, int TMAX>
@@ -1620,11 +1717,13 @@ static hipError_t search_w(const LaunchPlan& p, const DevBufs& b, hipStream_t st
 
 hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
     if (p.max_r <= 0 || p.search_blocks <= 0) return hipSuccess;
-    return p.words == 1 ? search_w<1>(p, b, stream) : search_w<2>(p, b, stream);
+    return p.words == 1 ? search_w<1>(p, b, stream)
+         : p.words == 2 ? search_w<2>(p, b, stream)
+                        : search_w<3>(p, b, stream);
 }
 
 hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
-    if (p.words == 1)
+    if (p.kwords == 1)
         hipLaunchKernelGGL(k_sort<1>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
                            b.ctr);
     else

@@ -121,7 +121,7 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     const int r = m >= l ? m - l + 1 : 0;
     const int bw = (r + 63) / 64;
     const int64_t N = (int64_t)n * r;
-    const int t = pms_default_threshold(n, m, l, d);
+    const int t = pms_default_threshold(n, m, l, d, 4);
     const unsigned long long items = std::max<unsigned long long>((unsigned long long)r * r, 1);
     const unsigned long long parts =
         std::max<unsigned long long>(std::min<unsigned long long>(items, 1ull << 22), 1024);
@@ -182,6 +182,9 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     v.s1_lo = 0;
     v.s1_hi = r;
     v.c1only = c1only;
+    v.asize = 4;
+    v.abits = 2;
+    v.amask = 0xFu;
     v.chars_off = 0;
     v.lmer_off = 0;
     v.compat_off = 0;
@@ -198,6 +201,7 @@ extern "C" int pms_solve_device_noalloc(const uint8_t* chars, int32_t n, int32_t
     p.deep_phases = deep_phases;
     p.deep_cap = deep_cap;
     p.words = words;
+    p.kwords = words;
     p.search_blocks = blocks;
     p.compat_kernel = 1;
     p.split = kSplitDefault;

@@ -60,29 +60,33 @@ int device_lds_per_block() {
     return v;
 }
 
-// |N_d| for an l-mer over a 4-letter alphabet: sum_{i<=d} C(l,i) 3^i (Appendix D).
-double ball_size(int l, int d) {
+// |N_d| for an l-mer over an alphabet of sigma letters:
+// sum_{i<=d} C(l,i) (sigma-1)^i (Appendix C).
+double ball_size(int l, int d, int sigma) {
     double s = 0, c = 1;
     for (int i = 0; i <= d && i <= l; i++) {
-        s += c * std::pow(3.0, i);
+        s += c * std::pow((double)(sigma - 1), i);
         c = c * (l - i) / (i + 1);
     }
     return s;
 }
 
+int sigma_or_dna(int sigma) { return sigma < 2 ? 4 : sigma; }
+
 }  // namespace
 
 // Stack size t at which the search switches to generation: minimise the
-// Appendix D cost model Time_s(t) + Time_p(t) over t, with p = N_2d / 4^l and
-// q = N_d / N_2d.  On the device a stack of three is never worse than two
+// Appendix D cost model Time_s(t) + Time_p(t) over t, with
+// p = N_2d / sigma^l and q = N_d / N_2d.  On the device a stack of three is never worse than two
 // once the model asks for more than one level (Theorem 1 makes the
 // three-l-mer tree free of dead ends), measured on MI355X for (9,2) .. (17,6);
 // the result is clamped to [2, 8].
-extern "C" int pms_default_threshold(int n, int m, int l, int d) {
+extern "C" int pms_default_threshold(int n, int m, int l, int d, int sigma) {
     const int r = m - l + 1;
     if (r <= 0 || n <= 1) return 2;
-    const double nd = ball_size(l, d), n2d = ball_size(l, 2 * d);
-    const double p = std::min(1.0, n2d / std::pow(4.0, l));
+    sigma = sigma_or_dna(sigma);
+    const double nd = ball_size(l, d, sigma), n2d = ball_size(l, 2 * d, sigma);
+    const double p = std::min(1.0, n2d / std::pow((double)sigma, l));
     const double q = nd / n2d;
     int best = 1;
     double best_cost = INFINITY, ts = 0;
@@ -100,13 +104,15 @@ extern "C" int pms_default_threshold(int n, int m, int l, int d) {
 }
 
 // Appendix C: the expected number of l-mers within d of some window of each
-// of n random strings, 4^l (1 - (1 - N_d / 4^l)^(m-l+1))^n.  Used to pre-size
-// an instance's output buffer (the planted motif plus the spurious ones).
-extern "C" double pms_expected_motifs(int n, int m, int l, int d) {
+// of n random strings, sigma^l (1 - (1 - N_d / sigma^l)^(m-l+1))^n.  Used to
+// pre-size an instance's output buffer (the planted motif plus the spurious
+// ones).
+extern "C" double pms_expected_motifs(int n, int m, int l, int d, int sigma) {
     const int r = m - l + 1;
     if (r <= 0 || n < 1 || l < 1 || d < 0) return 0.0;
-    const double all = std::pow(4.0, l);
-    const double p = std::min(1.0, ball_size(l, d) / all);
+    sigma = sigma_or_dna(sigma);
+    const double all = std::pow((double)sigma, l);
+    const double p = std::min(1.0, ball_size(l, d, sigma) / all);
     // 1 - (1 - p)^r without cancellation for tiny p
     const double hit = -std::expm1((double)r * std::log1p(-std::min(p, 1.0 - 1e-300)));
     return all * std::pow(hit, (double)n);
@@ -117,8 +123,8 @@ namespace {
 constexpr int64_t kOutCapMin = 256;
 constexpr int64_t kOutCapMax = int64_t(1) << 22;  // pre-sized slots; larger sets re-run alone
 
-int64_t presized_out_cap(int n, int m, int l, int d) {
-    const double e = pms_expected_motifs(n, m, l, d);
+int64_t presized_out_cap(int n, int m, int l, int d, int sigma) {
+    const double e = pms_expected_motifs(n, m, l, d, sigma);
     const double want = 2.0 * e + 64.0;
     const int64_t c = want >= (double)kOutCapMax ? kOutCapMax : (int64_t)want;
     return next_pow2(std::max(kOutCapMin, c));
@@ -130,8 +136,18 @@ constexpr int64_t kCompatBudget = int64_t(1) << 30;
 
 struct HostInst {
     int n, m, l, d, t, triple, s1_lo, s1_hi, c1only;
+    int asize, abits;   // letters; key bits per character
     std::string alpha;  // sorted
 };
+
+// Key bits per character: 2 for alphabets of up to 4 letters (the planar
+// DNA class), else ceil(log2 letters).
+int key_bits(int letters) {
+    if (letters <= 4) return 2;
+    int b = 0;
+    while ((1 << b) < letters) b++;
+    return b;
+}
 
 int validate(const pms_instance& in, HostInst& h, std::vector<uint8_t>& chars,
              std::vector<uint8_t>& lut) {
@@ -158,13 +174,19 @@ int validate(const pms_instance& in, HostInst& h, std::vector<uint8_t>& chars,
         if (s[in.m] != '\0') return PMS_E_INVAL;
         memcpy(&chars[base + (size_t)i * in.m], s, (size_t)in.m);
     }
-    if (a.size() != 4) return PMS_E_UNSUPPORTED;
+    const int letters = (int)a.size();
+    if (letters > kMaxAlpha) return PMS_E_UNSUPPORTED;
     if (in.l > kMaxL || in.n > kMaxN || in.m - in.l + 1 > kMaxR) return PMS_E_UNSUPPORTED;
+    // larger alphabets: five 32-bit planes, and keys of two words
+    if (letters > 4 && (in.l > kMaxLWide || in.l > 2 * (64 / key_bits(letters))))
+        return PMS_E_UNSUPPORTED;
     lut.insert(lut.end(), tab, tab + 256);
     h.n = in.n;
     h.m = in.m;
     h.l = in.l;
     h.d = in.d;
+    h.asize = letters;
+    h.abits = key_bits(letters);
     h.alpha = a;
     return PMS_OK;
 }
@@ -232,7 +254,8 @@ struct pms_batch {
     bool ran = false;
     int plan_status = PMS_OK;  // PMS_E_UNSUPPORTED when the search's LDS does not fit
     int failed = PMS_OK;  // sticky error: the batch's device state is unusable
-    int words = 1;
+    int words = 1;   // l-mer class (1, 2, or 3 for alphabets of more than 4 letters)
+    int kwords = 1;  // u64 words per key
     std::vector<InstCounters> last_ctr;  // counters read back by the last results call
 };
 
@@ -246,6 +269,7 @@ size_t plan_layout(pms_batch* bt) {
     LaunchPlan& p = bt->plan;
     p.n_inst = ni;
     p.words = bt->words;
+    p.kwords = bt->kwords;
     p.max_n_lmers = 0;
     p.max_r = 0;
     p.max_n = 0;
@@ -268,6 +292,9 @@ size_t plan_layout(pms_batch* bt) {
         d.s1_lo = h.s1_lo;
         d.s1_hi = h.s1_hi;
         d.c1only = h.c1only;
+        d.asize = h.asize;
+        d.abits = h.abits;
+        d.amask = h.asize >= 32 ? 0xFFFFFFFFu : (1u << h.asize) - 1u;
         d.pad = 0;
         d.chars_off = chars_off;
         d.lmer_off = lmer_off;
@@ -304,7 +331,7 @@ size_t plan_layout(pms_batch* bt) {
     while (p.s2cap > kStageCapMin && search_lds_bytes(p) > (size_t)device_lds_per_block())
         p.s2cap = std::max(kStageCapMin, p.s2cap / 2 / 64 * 64);
     bt->plan_status = search_lds_bytes(p) > (size_t)device_lds_per_block() ? PMS_E_UNSUPPORTED : PMS_OK;
-    const int64_t lmer_bytes = bt->words == 1 ? 8 : 16;
+    const int64_t lmer_size = (int64_t)lmer_bytes(bt->words);
     size_t off = 0;
     auto take = [&](int64_t bytes) {
         size_t o = off;
@@ -314,7 +341,7 @@ size_t plan_layout(pms_batch* bt) {
     size_t o_inst = take((int64_t)ni * sizeof(InstDev));
     size_t o_chars = take(chars_off);
     size_t o_lut = take((int64_t)ni * 256);
-    size_t o_lmers = take(lmer_off * lmer_bytes);
+    size_t o_lmers = take(lmer_off * lmer_size);
     size_t o_compat = take(compat_off * 8);
     size_t o_items = take((int64_t)bt->item_cap * 8);
     size_t o_parts = take((int64_t)bt->part_cap * 8);
@@ -330,7 +357,7 @@ size_t plan_layout(pms_batch* bt) {
                      : 1;
     size_t o_deep0 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
     size_t o_deep1 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
-    size_t o_keys = take(out_off * 8 * bt->words);
+    size_t o_keys = take(out_off * 8 * bt->kwords);
     size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
     size_t o_q = take(kQueues * sizeof(QueueCounters));
     // offsets are stored relative to the arena; resolve later
@@ -353,20 +380,21 @@ size_t plan_layout(pms_batch* bt) {
 
 namespace pms {
 
-// Upper bound of the device bytes an instance adds to a batch (16-byte
-// l-mers and 2-word keys, whatever the batch's width; its work items and
+// Upper bound of the device bytes an instance adds to a batch (20-byte
+// l-mers and 2-word keys, whatever the batch's class; its work items and
 // at most as many part items).
-size_t inst_bytes(int n, int m, int l, int d, const pms_tune* tune) {
+size_t inst_bytes(int n, int m, int l, int d, int sigma, const pms_tune* tune) {
     const int64_t r = m >= l ? m - l + 1 : 0;
     const int64_t N = (int64_t)n * r, bw = (r + 63) / 64;
     const int64_t cap = (tune && tune->out_capacity > 0) ? next_pow2(tune->out_capacity)
-                                                          : presized_out_cap(n, m, l, d);
+                                                          : presized_out_cap(n, m, l, d, sigma);
     const int t = (tune && tune->threshold > 0) ? std::max(2, std::min(kMaxT, (int)tune->threshold))
-                                                : pms_default_threshold(n, m, l, d);
+                                                : pms_default_threshold(n, m, l, d, sigma);
     // deep-item queues exist only in batches with a threshold above 3; two
     // queues of at most 2 * (sum of r^2, at least 1024) entries
     const int64_t deep = t > 3 ? 2 * (2 * r * std::max<int64_t>(r, 1) + 2048) * (int64_t)sizeof(DeepItem) : 0;
-    return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 + N * 16 + N * n * bw * 8 +
+    return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 +
+                    N * (int64_t)lmer_bytes(3) + N * n * bw * 8 +
                     2 * r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters) +
                     deep);
 }
@@ -492,6 +520,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
     bt->hin.resize(count);
     bt->out_cap.assign(count, kOutCapMin);
     bool wide = bt->tune.lmer_words == 2;
+    bool letters5 = false;  // some alphabet has more than 4 letters
     for (int i = 0; i < count; i++) {
         int rc = validate(inst[i], bt->hin[i], bt->chars, bt->lut);
         if (rc) {
@@ -500,31 +529,39 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         }
         HostInst& h = bt->hin[i];
         h.t = bt->tune.threshold > 0 ? std::max(2, std::min(kMaxT, (int)bt->tune.threshold))
-                                     : pms_default_threshold(h.n, h.m, h.l, h.d);
+                                     : pms_default_threshold(h.n, h.m, h.l, h.d, h.asize);
         h.triple = bt->tune.triple_filter < 0 ? 0 : 1;  // 0 = automatic = on
         const int r = h.m >= h.l ? h.m - h.l + 1 : 0;
         const bool all = bt->tune.s1_begin == 0 && bt->tune.s1_end == 0;
         h.s1_hi = all ? r : std::min(r, (int)bt->tune.s1_end);
         h.s1_lo = all ? 0 : std::min(h.s1_hi, (int)bt->tune.s1_begin);
         if (h.l > 32) wide = true;
+        if (h.asize > 4) letters5 = true;
         const int64_t full = (int64_t)h.n * r * h.n * ((r + 63) / 64) * 8;
         h.c1only = bt->tune.compat_mode == 2 || (bt->tune.compat_mode == 0 && full > kCompatBudget);
         bt->out_cap[i] = bt->tune.out_capacity > 0 ? next_pow2(bt->tune.out_capacity)
-                                                   : presized_out_cap(h.n, h.m, h.l, h.d);
+                                                   : presized_out_cap(h.n, h.m, h.l, h.d, h.asize);
     }
-    if (bt->tune.lmer_words == 1 && wide) {
+    if (letters5 && wide) {  // l > 32 and a large alphabet in one batch: no l-mer class fits
         delete bt;
         return PMS_E_UNSUPPORTED;
     }
-    bt->words = wide ? 2 : 1;
+    if (!letters5 && bt->tune.lmer_words == 1 && wide) {
+        delete bt;
+        return PMS_E_UNSUPPORTED;
+    }
+    bt->words = letters5 ? 3 : wide ? 2 : 1;
+    bt->kwords = bt->words == 1 ? 1 : 2;
     *out = bt;
     return PMS_OK;
 }
 
 void fill_result(const HostInst& h, const uint64_t* keys, int64_t cnt, int kw, pms_result* r) {
+    const int B = h.abits, cpw = 64 / B;
+    const uint64_t cmask = (1ull << B) - 1ull;
     r->count = cnt;
     r->l = h.l;
-    r->words = h.l <= 32 ? 1 : 2;
+    r->words = (h.l + cpw - 1) / cpw;
     r->motifs = nullptr;
     r->packed = nullptr;
     if (cnt == 0) return;
@@ -533,8 +570,8 @@ void fill_result(const HostInst& h, const uint64_t* keys, int64_t cnt, int kw, p
     for (int64_t i = 0; i < cnt; i++) {
         const uint64_t* k = keys + i * kw;
         for (int p = 0; p < h.l; p++) {
-            const uint64_t w = k[p >> 5];
-            const int c = (int)((w >> (62 - 2 * (p & 31))) & 3u);
+            const int q = p / cpw;
+            const int c = (int)((k[q] >> (64 - B * (p - q * cpw + 1))) & cmask);
             r->motifs[i * h.l + p] = h.alpha[c];
         }
         for (int q = 0; q < r->words; q++) r->packed[i * r->words + q] = k[q];
@@ -735,7 +772,7 @@ int pms_batch_results(pms_batch* bt, pms_result* outs) {
             over.push_back(i);
     }
     bt->last_ctr = ctr;
-    const int kw = bt->words;
+    const int kw = bt->kwords;
     std::vector<std::vector<uint64_t>> keys(ni);
     for (int i = 0; i < ni; i++) {
         if (std::find(over.begin(), over.end(), i) != over.end()) continue;

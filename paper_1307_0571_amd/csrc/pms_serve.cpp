@@ -48,6 +48,8 @@ struct Request {
     int status = PMS_E_AGAIN;
     pms_result result{};
     double est = 0;       // estimated work (arbitrary units, for ordering)
+    bool wide = false;    // l > 32 (two 64-bit planes)
+    bool letters5 = false;  // alphabet of more than 4 letters (five 32-bit planes)
     std::chrono::steady_clock::time_point t_submit;
 };
 
@@ -55,11 +57,11 @@ constexpr double kAgeLimitS = 30.0;  // waited longer: admitted first, oldest fi
 constexpr double kMixRatio = 16.0;   // largest / smallest estimate within one pass
 constexpr size_t kAlign = 256;
 
-// |{x : Hd(x, u) <= d}| for one l-mer u over a 4-letter alphabet (Appendix C).
-double ball(int l, int d) {
+// |{x : Hd(x, u) <= d}| for one l-mer u over sigma letters (Appendix C).
+double ball(int l, int d, int sigma) {
     double s = 0, c = 1;  // c = C(l, i)
     for (int i = 0; i <= d && i <= l; i++) {
-        s += c * std::pow(3.0, i);
+        s += c * std::pow((double)(sigma - 1), i);
         c = c * (l - i) / (i + 1);
     }
     return s;
@@ -67,10 +69,11 @@ double ball(int l, int d) {
 
 // Appendix D cost model at its best stack size plus the Appendix C expected
 // number of l-mers within d of some window of every string, weighted by l.
-double estimate(int n, int m, int l, int d) {
+double estimate(int n, int m, int l, int d, int sigma) {
     const int r = m - l + 1;
     if (r <= 0) return 0;
-    const double nd = ball(l, d), n2d = ball(l, 2 * d), all = std::pow(4.0, l);
+    const double nd = ball(l, d, sigma), n2d = ball(l, 2 * d, sigma),
+                 all = std::pow((double)sigma, l);
     const double p = std::min(1.0, n2d / all), q = nd / n2d;
     double best = INFINITY, ts = 0;
     for (int t = 1; t <= n; t++) {
@@ -79,7 +82,7 @@ double estimate(int n, int m, int l, int d) {
         const double tp = std::exp(std::min(lt + std::log(nd) + (t - 1) * std::log(q), 700.0)) * l;
         best = std::min(best, ts + tp);
     }
-    return best + pms_expected_motifs(n, m, l, d) * l * n * r;
+    return best + pms_expected_motifs(n, m, l, d, sigma) * l * n * r;
 }
 
 // First-fit allocator over the stream's device pool (offsets, host-side).
@@ -181,11 +184,14 @@ void worker(pms_stream* s) {
             // admit in that order while the pass's bound fits in the pool
             double lo_est = 0;
             size_t want = s->fixed;
+            bool has_wide = false, has_letters5 = false;
             for (auto& r : order) {
                 if ((int)pass.size() >= s->cfg.max_wave ||
                     s->inflight + (int)pass.size() >= s->cfg.max_inflight)
                     break;
                 if (!pass.empty() && !aged(r) && r->est > kMixRatio * std::max(lo_est, 1.0)) continue;
+                // one batch holds one l-mer class: l > 32 and large alphabets never meet
+                if ((r->wide && has_letters5) || (r->letters5 && has_wide)) continue;
                 size_t o = 0;
                 if (!s->alloc.alloc(want + r->bytes, &o)) {
                     if (pass.empty()) break;  // the first choice does not fit now
@@ -193,6 +199,8 @@ void worker(pms_stream* s) {
                 }
                 s->alloc.release(o, want + r->bytes);
                 pass.push_back(r);
+                has_wide |= r->wide;
+                has_letters5 |= r->letters5;
                 want += r->bytes;
                 if (pass.size() == 1) lo_est = r->est;
             }
@@ -298,9 +306,13 @@ int pms_stream_submit(pms_stream* s, const pms_instance* inst, uint64_t* ticket)
     size_t b = 0;
     rc = pms_batch_workspace_size(&r->inst, 1, &s->cfg.tune, &b);
     if (rc) return rc;
-    r->bytes = pms::inst_bytes(inst->n, inst->m, inst->l, inst->d, &s->cfg.tune);
+    // letters of the (validated: distinct characters) alphabet
+    const int sigma = (int)r->alphabet.size();
+    r->bytes = pms::inst_bytes(inst->n, inst->m, inst->l, inst->d, sigma, &s->cfg.tune);
     if (s->fixed + r->bytes > (size_t)s->cfg.device_mem_cap) return PMS_E_NOMEM;
-    r->est = estimate(r->inst.n, r->inst.m, r->inst.l, r->inst.d);
+    r->est = estimate(r->inst.n, r->inst.m, r->inst.l, r->inst.d, sigma);
+    r->wide = inst->l > 32;
+    r->letters5 = sigma > 4;
     r->t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return PMS_E_ABORTED;

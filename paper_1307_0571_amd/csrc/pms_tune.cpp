@@ -41,14 +41,20 @@ std::map<std::string, pms_tune> g_cache;
 bool g_loaded = false;
 
 std::string shape_key(const pms_instance* inst, int count) {
-    std::set<std::tuple<int, int, int, int>> shapes;
+    std::set<std::tuple<int, int, int, int, int>> shapes;
     for (int i = 0; i < count; i++)
-        shapes.insert(std::make_tuple(inst[i].l, inst[i].d, inst[i].n / 8, inst[i].m / 256));
+        shapes.insert(std::make_tuple(inst[i].l, inst[i].d, inst[i].n / 8, inst[i].m / 256,
+                                      inst[i].alphabet ? (int)strlen(inst[i].alphabet) : 0));
     std::string k;
-    char buf[64];
+    char buf[80];
     for (const auto& s : shapes) {
-        snprintf(buf, sizeof buf, "%d,%d,%d,%d;", std::get<0>(s), std::get<1>(s), std::get<2>(s),
-                 std::get<3>(s));
+        // the alphabet's size is part of the key only when it is not 4
+        if (std::get<4>(s) == 4)
+            snprintf(buf, sizeof buf, "%d,%d,%d,%d;", std::get<0>(s), std::get<1>(s),
+                     std::get<2>(s), std::get<3>(s));
+        else
+            snprintf(buf, sizeof buf, "%d,%d,%d,%d,a%d;", std::get<0>(s), std::get<1>(s),
+                     std::get<2>(s), std::get<3>(s), std::get<4>(s));
         k += buf;
     }
     int lg = 0;
@@ -177,8 +183,8 @@ extern "C" int pms_autotune(const pms_instance* inst, int32_t count, const pms_t
         {&pms_tune::triple_filter, {-1}},
         {&pms_tune::lmer_words, {2}},
     };
-    bool wide = false;
-    for (const auto& x : s) wide |= x.l > 32;
+    bool wide = false;  // l > 32, or an alphabet of more than 4 letters: one l-mer class
+    for (const auto& x : s) wide |= x.l > 32 || (x.alphabet && strlen(x.alphabet) > 4);
     for (int pass = 0; pass < 2 && runs < max_runs; pass++) {
         bool improved = false;
         for (const Dim& dim : dims) {

@@ -33,6 +33,7 @@ import numpy as np
 GOLDEN = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
 DNA = "ACGT"
+PROTEIN = "ACDEFGHIKLMNPQRSTVWY"  # the 20 standard amino acids
 
 
 def _mix_int(z: int) -> int:
@@ -167,7 +168,7 @@ def random_strings(seed: int, n: int, m: int, alphabet: str = DNA) -> Instance:
 
 def batch_mix(seed0: int, count: int,
               ld: Sequence[tuple] = ((11, 3), (13, 4), (15, 5)),
-              n_range=(10, 30), m_range=(300, 1000)) -> List[Instance]:
+              n_range=(10, 30), m_range=(300, 1000), alphabet: str = DNA) -> List[Instance]:
     """Mixed batch: (l,d) uniform from ``ld``, n and m uniform in the ranges.
 
     Instance k uses seed ``seed0 + k``; its shape is drawn from the seed's own
@@ -181,5 +182,5 @@ def batch_mix(seed0: int, count: int,
         l, d = ld[sh.below(len(ld))]
         n = n_range[0] + sh.below(n_range[1] - n_range[0] + 1)
         m = m_range[0] + sh.below(m_range[1] - m_range[0] + 1)
-        out.append(planted(s, l, d, n, m))
+        out.append(planted(s, l, d, n, m, alphabet))
     return out

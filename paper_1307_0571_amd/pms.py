@@ -129,8 +129,8 @@ def load():
     lib.pms_version.restype = ctypes.c_char_p
     lib.pms_autotune.argtypes = [P(_Instance), ctypes.c_int32, P(Tune), ctypes.c_int32,
                                  ctypes.c_int32, P(Tune)]
-    lib.pms_default_threshold.argtypes = [ctypes.c_int] * 4
-    lib.pms_expected_motifs.argtypes = [ctypes.c_int] * 4
+    lib.pms_default_threshold.argtypes = [ctypes.c_int] * 5
+    lib.pms_expected_motifs.argtypes = [ctypes.c_int] * 5
     lib.pms_expected_motifs.restype = ctypes.c_double
     lib.pms_device_count.argtypes = [P(ctypes.c_int32)]
     lib.pms_device_synchronize.argtypes = []
@@ -161,12 +161,12 @@ def device_synchronize() -> None:
     _check(load().pms_device_synchronize(), "pms_device_synchronize")
 
 
-def default_threshold(n: int, m: int, l: int, d: int) -> int:
-    return int(load().pms_default_threshold(n, m, l, d))
+def default_threshold(n: int, m: int, l: int, d: int, sigma: int = 4) -> int:
+    return int(load().pms_default_threshold(n, m, l, d, sigma))
 
 
-def expected_motifs(n: int, m: int, l: int, d: int) -> float:
-    return float(load().pms_expected_motifs(n, m, l, d))
+def expected_motifs(n: int, m: int, l: int, d: int, sigma: int = 4) -> float:
+    return float(load().pms_expected_motifs(n, m, l, d, sigma))
 
 
 @dataclass

@@ -12,7 +12,8 @@ Usage:  python tests/golden/make_goldens.py [group ...] [--threads N]
 Groups: plain (the (9,2), (13,4), (15,5) single instances, n=20, m=600,
 seeds 0-4), large ((17,6) seeds 0-2), batched (a seeded sample of the
 256-instance mixed batch), serving (a seeded sample of the 10,000-request
-served stream).
+served stream), protein (a seeded sample of the 256-instance batch over the
+20 amino acids).
 """
 from __future__ import annotations
 
@@ -37,6 +38,8 @@ BATCH_SEED0, BATCH_COUNT = 1000, 256
 BATCH_LD = ((11, 3), (13, 4), (15, 5))
 SERVE_SEED0, SERVE_COUNT = 2000, 10000
 SERVE_LD = ((9, 2), (11, 3), (13, 4), (15, 5), (17, 6))
+PROTEIN_SEED0, PROTEIN_COUNT = 3000, 256
+PROTEIN_LD = ((11, 4), (13, 5), (15, 6))
 
 
 def digest(motifs) -> str:
@@ -46,20 +49,21 @@ def digest(motifs) -> str:
     return h.hexdigest()
 
 
-def expected_spurious(l: int, d: int, n: int, m: int) -> float:
-    """Appendix C: 4^l (1 - (1 - N_d / 4^l)^(m-l+1))^n (DNA)."""
-    nd = sum(math.comb(l, i) * 3 ** i for i in range(d + 1))
-    p = nd / 4.0 ** l
-    return 4.0 ** l * (1.0 - (1.0 - p) ** (m - l + 1)) ** n
+def expected_spurious(l: int, d: int, n: int, m: int, sigma: int = 4) -> float:
+    """Appendix C: sigma^l (1 - (1 - N_d / sigma^l)^(m-l+1))^n."""
+    nd = sum(math.comb(l, i) * (sigma - 1) ** i for i in range(d + 1))
+    p = nd / float(sigma) ** l
+    return float(sigma) ** l * (1.0 - (1.0 - p) ** (m - l + 1)) ** n
 
 
 def entry(inst, threads, t=3, kind="b"):
     t0 = time.time()
     if kind == "a":
-        res = oracle.solve_a(inst.seqs, inst.l, inst.d, threads=threads)
+        res = oracle.solve_a(inst.seqs, inst.l, inst.d, alphabet=inst.alphabet, threads=threads)
         st = None
     else:
-        res, st = oracle.solve_b(inst.seqs, inst.l, inst.d, t=t, threads=threads, stats=True)
+        res, st = oracle.solve_b(inst.seqs, inst.l, inst.d, alphabet=inst.alphabet, t=t,
+                                 threads=threads, stats=True)
         st = {k: v for k, v in st.items() if k != "pushes"}
     e = {"seed": inst.seed, "l": inst.l, "d": inst.d, "n": inst.n, "m": inst.m,
          "motif": inst.motif, "count": len(res), "sha256": digest(res),
@@ -141,8 +145,34 @@ def group_serving(threads):
                       "l >= 15 requests with n <= 20 and m <= 700", "instances": out}
 
 
+def group_protein(threads):
+    """16 of batch_mix(3000, 256) over the 20 amino acids: 12 seeded draws
+    plus the 4 with the largest Appendix C expected number of spurious
+    motifs."""
+    insts = I.batch_mix(PROTEIN_SEED0, PROTEIN_COUNT, ld=PROTEIN_LD, alphabet=I.PROTEIN)
+    rng = random.Random(20242)
+    picked = set(rng.sample(range(PROTEIN_COUNT), 12))
+    heavy = sorted(range(PROTEIN_COUNT),
+                   key=lambda k: -expected_spurious(insts[k].l, insts[k].d, insts[k].n,
+                                                    insts[k].m, 20))
+    for k in heavy:
+        if len(picked) >= 16:
+            break
+        picked.add(k)
+    out = []
+    for k in sorted(picked):
+        e = entry(insts[k], threads)
+        e["index"] = k
+        e["alphabet"] = I.PROTEIN
+        out.append(e)
+    return {"workload": f"batch_mix({PROTEIN_SEED0}, {PROTEIN_COUNT}) over the 20 amino acids, "
+                        f"(l,d) in {list(PROTEIN_LD)}, n in [10,30], m in [300,1000]",
+            "sample": "12 seeded (random.Random(20242)) + the 4 largest Appendix C "
+                      "expected spurious counts", "instances": out}
+
+
 GROUPS = {"plain": group_plain, "large": group_large, "batched": group_batched,
-          "serving": group_serving}
+          "serving": group_serving, "protein": group_protein}
 
 
 def main():

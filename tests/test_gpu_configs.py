@@ -82,8 +82,8 @@ def test_large_17_6_config(e):
     _check(_solve(inst), e)
 
 
-def _is_motif(seqs, mot, d):
-    code = {c: i for i, c in enumerate("ACGT")}
+def _is_motif(seqs, mot, d, alphabet="ACGT"):
+    code = {c: i for i, c in enumerate(alphabet)}
     M = np.array([code[c] for c in mot], dtype=np.int8)
     l = len(mot)
     for s in seqs:
@@ -113,6 +113,26 @@ def test_batched_config_256():
         assert x.motif in g, x.seed
         for k in rng.choice(len(g), size=min(3, len(g)), replace=False):
             assert _is_motif(x.seqs, g[int(k)], x.d), (x.seed, g[int(k)])
+
+
+def test_protein_batched_config_256():
+    """The 256-instance batch over the 20 amino acids ((11,4)/(13,5)/(15,6),
+    n 10-30, m 300-1000) in one device pass: the 16 stored instances equal
+    the oracle's sets, every instance reports its planted motif, and a
+    sample of reported motifs satisfies the definition directly."""
+    stored = _load("protein")
+    insts = I.batch_mix(3000, 256, ld=((11, 4), (13, 5), (15, 6)), alphabet=I.PROTEIN)
+    _say("protein batched: 256 instances in one pass")
+    got = pms.solve_batch([pms.Problem(x.seqs, x.l, x.d, x.alphabet) for x in insts])
+    for e in stored:
+        x = insts[e["index"]]
+        assert (x.seed, x.l, x.d, x.n, x.m) == (e["seed"], e["l"], e["d"], e["n"], e["m"])
+        _check(got[e["index"]], e)
+    rng = np.random.default_rng(6)
+    for x, g in zip(insts, got):
+        assert x.motif in g, x.seed
+        for k in rng.choice(len(g), size=min(3, len(g)), replace=False):
+            assert _is_motif(x.seqs, g[int(k)], x.d, I.PROTEIN), (x.seed, g[int(k)])
 
 
 def test_batched_sample_alone_equals_in_batch():

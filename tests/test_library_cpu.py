@@ -61,7 +61,9 @@ def test_rejects_invalid_input(lib):
     assert _status(["ACGTNCGT", "ACGTACGT"], 4, 1) == pms.PMS_E_ALPHABET
     assert _status(["acgtacgt", "ACGTACGT"], 4, 1) == pms.PMS_E_ALPHABET  # case-sensitive
     assert _status(ok, 4, 1, alphabet="ACGA") == pms.PMS_E_ALPHABET      # repeated letter
-    assert _status(["ACGACGAC", "CCGAAGAC"], 4, 1, alphabet="ACG") == pms.PMS_E_UNSUPPORTED
+    assert _status(["AB", "BA"], 1, 0, alphabet="A") == pms.PMS_E_ALPHABET  # one letter
+    big = "".join(chr(ord("A") + i) for i in range(26)) + "012345!"      # 33 letters
+    assert _status(["ABCD", "DCBA"], 2, 1, alphabet=big) == pms.PMS_E_UNSUPPORTED
     assert _status(["A" * 80, "C" * 80], 65, 3) == pms.PMS_E_UNSUPPORTED   # l > 64
     many = I.random_strings(1, 33, 20).seqs
     assert _status(many, 5, 1) == pms.PMS_E_UNSUPPORTED                   # n > 32
@@ -84,6 +86,57 @@ def test_default_threshold_range(lib):
         assert 2 <= t <= 8
     # more windows per string -> never a larger threshold (Appendix D: t falls with m)
     assert pms.default_threshold(20, 2000, 15, 5) <= pms.default_threshold(20, 300, 15, 5)
+
+
+def _ws(problems, tune=None):
+    mar = pms._Marshal(problems)
+    sz = ctypes.c_size_t(0)
+    t = ctypes.byref(tune) if tune is not None else None
+    return pms.load().pms_batch_workspace_size(mar.arr, len(problems), t, ctypes.byref(sz))
+
+
+def test_alphabet_limits_host_only(lib):
+    P = I.PROTEIN
+    prot = I.random_strings(1, 4, 60, P).seqs
+    assert _ws([pms.Problem(prot, 11, 4, P)]) == pms.PMS_OK
+    assert _ws([pms.Problem(prot, 24, 9, P)]) == pms.PMS_OK         # 2 words of 12 5-bit codes
+    assert _ws([pms.Problem(prot, 25, 9, P)]) == pms.PMS_E_UNSUPPORTED
+    a16 = "ABCDEFGHIJKLMNOP"
+    s16 = I.random_strings(2, 3, 60, a16).seqs
+    assert _ws([pms.Problem(s16, 32, 9, a16)]) == pms.PMS_OK        # 2 words of 16 4-bit codes
+    assert _ws([pms.Problem(s16, 33, 9, a16)]) == pms.PMS_E_UNSUPPORTED  # 32-bit planes
+    for a in ("01", "ACG"):
+        assert _ws([pms.Problem(I.random_strings(3, 3, 40, a).seqs, 8, 2, a)]) == pms.PMS_OK
+    dna = I.random_strings(4, 3, 60).seqs
+    # one batch: l > 32 and a large alphabet never share one (no l-mer class holds both)
+    assert _ws([pms.Problem(dna, 40, 9), pms.Problem(prot, 11, 4, P)]) == pms.PMS_E_UNSUPPORTED
+    assert _ws([pms.Problem(dna, 20, 5), pms.Problem(prot, 11, 4, P)]) == pms.PMS_OK
+
+
+def test_expected_motifs_one_window_is_the_ball(lib):
+    # n = 1, m = l: Appendix C's expectation is exact, the motif set being
+    # the d-ball of the one window, sum_i C(l,i) (sigma-1)^i l-mers; the
+    # oracle's set size fixes it for every alphabet size
+    import oracle
+    for seed, alpha, l, d in [(1, "ACGT", 6, 2), (2, I.PROTEIN, 4, 2), (3, "01", 10, 3),
+                              (4, "ACG", 7, 2), (5, "ABCDEFGH", 5, 3)]:
+        inst = I.random_strings(seed, 1, l, alpha)
+        want = len(oracle.solve_a(inst.seqs, l, d, alphabet=alpha))
+        assert round(pms.expected_motifs(1, l, l, d, len(alpha))) == want
+        assert round(pms.expected_motifs(1, l, l, d, 0)) == round(pms.expected_motifs(1, l, l, d, 4))
+
+
+def test_default_threshold_any_alphabet(lib):
+    for sigma in (2, 3, 4, 8, 20, 32):
+        for (l, d) in [(9, 2), (13, 5), (17, 7)]:
+            assert 2 <= pms.default_threshold(20, 600, l, d, sigma) <= 8
+    # the same Appendix D model as the oracle's (at its best stack size of 3 and up)
+    from oracle.oracle import default_threshold
+    for sigma in (8, 20, 32):
+        for (l, d) in [(9, 2), (11, 3), (15, 5), (20, 8)]:
+            want = default_threshold(20, 600, l, d, sigma)
+            if want >= 3:
+                assert pms.default_threshold(20, 600, l, d, sigma) == want
 
 
 def test_workspace_size_is_host_only(lib):
