@@ -120,8 +120,11 @@ typedef struct pms_tune {
                                long-sequence mode); 0 = 2 for an instance
                                whose whole matrix exceeds 1 GiB, else 1 */
     int64_t out_capacity;   /* motif slots per instance (before removal of
-                               repeats); 0 = sized from the Appendix C expected
-                               number of motifs (pms_expected_motifs) */
+                               repeats); 0 = 4 x the Appendix C expected
+                               number of motifs (pms_expected_motifs) + 64,
+                               rounded up to a power of two, at most 2^23; an
+                               instance that emits more is solved again alone
+                               with room for all it emitted */
 } pms_tune;
 
 /* Autotuner.  Times the device pipeline on an evenly spread sample of at

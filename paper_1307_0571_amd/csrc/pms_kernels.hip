@@ -79,6 +79,10 @@ __device__ __forceinline__ int rank_below(unsigned long long m) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x) |
+           (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32;
+}
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
     int lane = lane_id();
@@ -349,6 +353,7 @@ struct SearchLds {
     int nseg;
     int item;
     int xs[kTailSlots];              // window of each slot's candidate
+    int sv[64];                      // windows of the survivors a transposed check holds
     int aslot[kTailSlots];           // live slots, in order
     Lm<W> dq_v[64];                  // donated subtrees: prefix,
     uint8_t dq_d[64], dq_s[64];      // depth and slot
@@ -915,14 +920,83 @@ struct Searcher {
         return ok;
     }
 
+    // Which buffered l-mers have a survivor of string `row` (level-k bitset
+    // rw, not staged) within d, transposed: lanes hold up to 64 of the
+    // survivors at a time (one load each) and the l-mers without a hit yet
+    // are walked uniformly, each tested against all of them in one wave
+    // instruction.  Bit i of hw[i / 64] is set for l-mer i with a hit.
+    __device__ __forceinline__ void hits_unstaged(const uint64_t* rw, int row, int nl,
+                                                  uint64_t (&hw)[kLeafCap / 64]) {
+        const int bw = I.bw, d = I.d;
+        int w = 0;
+        uint64_t rest = uni64(rw[0]);
+        int live = nl;  // l-mers without a hit yet
+        while (live > 0) {
+            // the next (up to) 64 survivors, in window order, into S.sv
+            int cnt = 0;
+            while (cnt < 64) {
+                if (rest == 0ull) {
+                    if (++w >= bw) break;
+                    rest = uni64(rw[w]);
+                    continue;
+                }
+                const int pcnt = __popcll(rest);
+                const int take = pcnt < 64 - cnt ? pcnt : 64 - cnt;
+                const bool set = (rest >> lane) & 1ull;
+                const int rk = rank_below(rest);
+                if (set && rk < take) S.sv[cnt + rk] = w * 64 + lane;
+                if (take == pcnt) {
+                    rest = 0ull;
+                } else {
+                    // keep the bits from the take-th set bit on
+                    const unsigned long long first = ballot(set && rk == take);
+                    rest &= ~0ull << __builtin_ctzll(first);
+                }
+                cnt += take;
+            }
+            if (cnt == 0) break;
+            __syncthreads();
+            const bool mine = lane < cnt;
+            const Lm<W> v = mine ? L[row * I.r + S.sv[lane]] : lm_zero<W>();
+#pragma unroll
+            for (int q = 0; q < kLeafCap / 64; q++) {
+                if (q * 64 < nl) {
+                    const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
+                    uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
+                    while (todo) {
+                        // two l-mers per round
+                        const int i0 = __builtin_ctzll(todo);
+                        todo &= todo - 1;
+                        const bool two = todo != 0ull;
+                        const int i1 = two ? __builtin_ctzll(todo) : i0;
+                        if (two) todo &= todo - 1;
+                        const Lm<W> m0 = leaf[q * 64 + i0];
+                        const Lm<W> m1 = leaf[q * 64 + i1];
+                        const unsigned long long b0 = ballot(mine && pc(dmask(m0, v)) <= d);
+                        const unsigned long long b1 = ballot(mine && pc(dmask(m1, v)) <= d);
+                        if (b0) {
+                            hw[q] |= 1ull << i0;
+                            live--;
+                        }
+                        if (two && b1) {
+                            hw[q] |= 1ull << i1;
+                            live--;
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // S.sv is rewritten by the next chunk
+        }
+    }
+
     // Check the buffered l-mers against every remaining string, one string
-    // (segment) at a time, fewest survivors first: lanes take one l-mer each
-    // and look for a survivor of that string within d (the l-mer's slot's
-    // survivor bits over the staged segment, or the string's level-k bitset
-    // when nothing is staged); the l-mers that found one are compacted in
-    // place and go on to the next string.  The rest are motifs.
+    // (segment) at a time, fewest survivors first; the l-mers that have a
+    // survivor of that string within d are compacted in place and go on to
+    // the next string, the rest are motifs.  Staged survivors: lanes take
+    // one l-mer each and scan its slot's survivor bits over the segment;
+    // otherwise the transposed test above on the string's level-k bitset.
     __device__ __forceinline__ void check_leaves(int k, int nl, bool staged) {
-        const int nseg = S.nseg, d = I.d, bw = I.bw, r = I.r;
+        const int nseg = S.nseg, d = I.d, bw = I.bw;
         const uint64_t* lvk = k >= 2 ? level(k) : nullptr;
         for (int g = 0; g < nseg && nl > 0; g++) {
             int a = 0, b = 0, row = 0;
@@ -931,6 +1005,36 @@ struct Searcher {
                 b = S.segoff[g + 1];
             } else {
                 row = S.segrow[g];
+                uint64_t hw[kLeafCap / 64];
+#pragma unroll
+                for (int q = 0; q < kLeafCap / 64; q++) hw[q] = 0ull;
+                hits_unstaged(lvk + row * bw, row, nl, hw);
+                int keep_n = 0;
+#pragma unroll
+                for (int q = 0; q < kLeafCap / 64; q++) {
+                    if (q * 64 < nl) {
+                        const int i = q * 64 + lane;
+                        const bool act = i < nl;
+                        Lm<W> mv = lm_zero<W>();
+                        int sl = 0;
+                        if (act) {
+                            mv = leaf[i];
+                            sl = leafslot[i];
+                        }
+                        const bool hit = act && ((hw[q] >> lane) & 1ull);
+                        const unsigned long long hm = ballot(hit);
+                        __syncthreads();  // every lane has read its l-mer before the compaction
+                        if (hit) {
+                            const int at = keep_n + rank_below(hm);
+                            leaf[at] = mv;
+                            leafslot[at] = (uint8_t)sl;
+                        }
+                        keep_n += __popcll(hm);
+                        __syncthreads();
+                    }
+                }
+                nl = keep_n;
+                continue;
             }
             int keep_n = 0;
             for (int c0 = 0; c0 < nl; c0 += 64) {
@@ -945,42 +1049,23 @@ struct Searcher {
                 bool hit = false;
                 if (act) {
                     // up to four candidates' loads in flight per round
-                    if (staged) {
-                        for (int w = a >> 6; w <= (b - 1) >> 6 && !hit; w++) {
-                            uint64_t m = ~0ull;
-                            if (a - 64 * w > 0) m &= ~0ull << (a - 64 * w);
-                            if (b - 64 * w < 64) m &= (1ull << (b - 64 * w)) - 1ull;
-                            uint64_t bits = memb[sl * mw + w] & m;
-                            while (bits && !hit) {
-                                Lm<W> v[4];
-                                bool use[4];
+                    for (int w = a >> 6; w <= (b - 1) >> 6 && !hit; w++) {
+                        uint64_t m = ~0ull;
+                        if (a - 64 * w > 0) m &= ~0ull << (a - 64 * w);
+                        if (b - 64 * w < 64) m &= (1ull << (b - 64 * w)) - 1ull;
+                        uint64_t bits = memb[sl * mw + w] & m;
+                        while (bits && !hit) {
+                            Lm<W> v[4];
+                            bool use[4];
 #pragma unroll
-                                for (int u = 0; u < 4; u++) {
-                                    use[u] = bits != 0ull;
-                                    const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : a;
-                                    bits &= bits - 1;
-                                    v[u] = s2get(x);
-                                }
-#pragma unroll
-                                for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
+                            for (int u = 0; u < 4; u++) {
+                                use[u] = bits != 0ull;
+                                const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : a;
+                                bits &= bits - 1;
+                                v[u] = s2get(x);
                             }
-                        }
-                    } else {
-                        for (int w = 0; w < bw && !hit; w++) {
-                            uint64_t bits = lvk[row * bw + w];
-                            while (bits && !hit) {
-                                Lm<W> v[4];
-                                bool use[4];
 #pragma unroll
-                                for (int u = 0; u < 4; u++) {
-                                    use[u] = bits != 0ull;
-                                    const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : 0;
-                                    bits &= bits - 1;
-                                    v[u] = L[row * r + x];
-                                }
-#pragma unroll
-                                for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
-                            }
+                            for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
                         }
                     }
                 }
