@@ -156,7 +156,7 @@ def hd_compares(insts, units, t_of):
     count of the same search (sampled windows, scaled)."""
     compat = sum(x.n * (x.n - 1) // 2 * (x.m - x.l + 1) ** 2 for x in insts)
     verify = None
-    if units is not None:
+    if units is not None and all(str(t) in u["by_t"] for t, u in zip(t_of, units)):
         verify = sum(units[k]["by_t"][str(t_of[k])]["verify_tests"] for k in range(len(insts)))
     return compat, verify
 

@@ -315,10 +315,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
 // the next member comes from string p, every candidate of p (up to
 // kTailSlots at a time) becomes a slot:
 //   * the survivors of the other remaining strings are staged once in LDS
-//     (one segment per string, fewest survivors first), and each slot keeps
-//     one bit per staged l-mer: the push filter of its candidate (Hd <= 2d
-//     and Theorem 1 against every stack member), evaluated on the staged
-//     l-mers directly;
+//     (one segment per string, fewest survivors first);
 //   * the pruned trees of Algorithm 1 of all live slots are split into
 //     subtrees at depth 2 or 3 and handed to lanes; each lane walks its
 //     subtree depth-first on its own (no shared stack): a node's 4-bit mask
@@ -326,14 +323,18 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
 //     triple slacks of the suffix (the prune of Algorithm 1 with Theorem 1),
 //     and the unvisited children of every depth on the path are kept as
 //     nibbles in registers;
-//   * complete l-mers go to an LDS buffer and are checked lane by lane
-//     against the slot's staged survivors of every remaining string
-//     (Algorithm 2's isMotif on the filtered rows).
-// When the staged survivors do not fit the LDS area, the slots keep no
-// bits and their l-mers are checked against the level bitsets directly
-// (still exact: every l-mer within d of a common d-neighbour of the stack
-// passes the pair and Theorem 1 tests).  A complete stack (t reached at a
-// push, no string left, or a single string) is a tail batch of one slot.
+//   * complete l-mers go to an LDS buffer and are checked against the
+//     survivors of every remaining string (Algorithm 2's isMotif on the
+//     filtered rows), transposed: the lanes hold 64 survivors of a string,
+//     and each buffered l-mer is tested against all of them in one wave
+//     instruction.  The candidate's own push filter is not applied to the
+//     survivors first: a survivor within d of a generated l-mer passes it
+//     anyway (triangle inequality, and Theorem 1 for the common neighbour),
+//     so the check finds the same hits without it.
+// When the staged survivors do not fit the LDS area, the check loads each
+// string's survivors (from the level bitsets) 64 at a time instead.  A
+// complete stack (t reached at a push, no string left, or a single string)
+// is a tail batch of one slot.
 
 constexpr int kTailSlots = 16;  // candidates of one tail batch (<= 32: one bit each)
 constexpr int kLeafCap = 256;   // generated l-mers awaiting the check
@@ -423,11 +424,9 @@ struct Searcher {
     unsigned* cntw;
     uint32_t inv_bw;      // ceil(2^32 / bw) (bw >= 2)
     Lm<W>* s2;            // staged survivors (and the filter's listing scratch)
-    uint64_t* memb;       // [kTailSlots][mw] survivor bits per slot
     Lm<W>* ut;            // [kTailSlots] candidate of each slot
     Lm<W>* leaf;          // [kLeafCap] generated l-mers
-    uint8_t* leafslot;    // [kLeafCap] their slots
-    int s2cap, mw;        // staging area (entries of sizeof(Lm<W>)), survivor-bit words per slot
+    int s2cap;            // staging area (entries of sizeof(Lm<W>))
     bool half;            // W == 1 and l <= 16: staged l-mers packed in 4 bytes
     int scap;             // staged l-mers that fit
     uint32_t* cm;         // W == 3: [32 depths][64 lanes] child masks
@@ -777,68 +776,6 @@ struct Searcher {
         return hi > a ? hi - a : 0;
     }
 
-    // Survivor bits of slot s: staged l-mer v is kept iff Hd(cand, v) <= 2d
-    // and, with the Theorem 1 filter, Cd(s_a, cand, v) <= 3d for every stack
-    // member s_a (a < k).  Returns whether every segment keeps a survivor.
-    __device__ __forceinline__ bool filter_slot(int k, int s, int tot) {
-        const Lm<W> cand = ut[s];
-        const int d2 = 2 * I.d, thr3 = 3 * I.d;
-        Lm<W> sa[TMAX];
-        M ea[TMAX];
-        int ha[TMAX];
-#pragma unroll
-        for (int a = 0; a < TMAX; a++) {
-            const int aa = a < k ? a : 0;
-            sa[a] = S.st[aa];
-            ea[a] = dmask(sa[a], cand);
-            ha[a] = pc(ea[a]);
-        }
-        for (int i0 = 0; i0 < tot; i0 += 256) {
-            Lm<W> v[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int i = i0 + 64 * u + lane;
-                v[u] = s2get(i < tot ? i : 0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int i = i0 + 64 * u + lane;
-                bool keep = false;
-                if (i < tot) {
-                    const int hv = pc(dmask(cand, v[u]));
-                    keep = hv <= d2;
-                    if (I.triple) {
-#pragma unroll
-                        for (int a = 0; a < TMAX; a++) {
-                            if (a < k) {
-                                const M da = dmask(sa[a], v[u]);
-                                keep &= ha[a] + pc(da) + hv - pc((M)(ea[a] | da)) <= thr3;
-                            }
-                        }
-                    }
-                }
-                const unsigned long long bm = ballot(keep);
-                if (lane == 0 && i0 + 64 * u < tot) memb[s * mw + ((i0 >> 6) + u)] = bm;
-            }
-        }
-        __syncthreads();
-        // every segment keeps at least one survivor
-        bool empty = false;
-        if (lane < S.nseg) {
-            const int a = S.segoff[lane], b = S.segoff[lane + 1];
-            uint64_t acc = 0;
-            for (int w = a >> 6; w <= (b - 1) >> 6; w++) {
-                const int lo = a - 64 * w, hi = b - 64 * w;
-                uint64_t m = ~0ull;
-                if (lo > 0) m &= ~0ull << lo;
-                if (hi < 64) m &= (1ull << hi) - 1ull;
-                acc |= memb[s * mw + w] & m;
-            }
-            empty = acc == 0ull;
-        }
-        return ballot(empty) == 0ull;
-    }
-
     // ---- the tail batch: generation over subtrees, check, emission ----
 
     // Valid children (4-bit mask) of the node at depth P whose prefix is mv
@@ -925,9 +862,52 @@ struct Searcher {
     // survivors at a time (one load each) and the l-mers without a hit yet
     // are walked uniformly, each tested against all of them in one wave
     // instruction.  Bit i of hw[i / 64] is set for l-mer i with a hit.
+    __device__ __forceinline__ void walk_leaves(const Lm<W>& v, bool mine, int nl,
+                                                uint64_t (&hw)[kLeafCap / 64], int& live) const {
+        const int d = I.d;
+#pragma unroll
+        for (int q = 0; q < kLeafCap / 64; q++) {
+            if (q * 64 < nl) {
+                const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
+                uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
+                while (todo) {
+                    // two l-mers per round
+                    const int i0 = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    const bool two = todo != 0ull;
+                    const int i1 = two ? __builtin_ctzll(todo) : i0;
+                    if (two) todo &= todo - 1;
+                    const Lm<W> m0 = leaf[q * 64 + i0];
+                    const Lm<W> m1 = leaf[q * 64 + i1];
+                    const unsigned long long b0 = ballot(mine && pc(dmask(m0, v)) <= d);
+                    const unsigned long long b1 = ballot(mine && pc(dmask(m1, v)) <= d);
+                    if (b0) {
+                        hw[q] |= 1ull << i0;
+                        live--;
+                    }
+                    if (two && b1) {
+                        hw[q] |= 1ull << i1;
+                        live--;
+                    }
+                }
+            }
+        }
+    }
+
+    // The same for a staged segment [a, b) of the staging area.
+    __device__ __forceinline__ void hits_staged(int a, int b, int nl,
+                                                uint64_t (&hw)[kLeafCap / 64]) {
+        int live = nl;
+        for (int c0 = a; c0 < b && live > 0; c0 += 64) {
+            const bool mine = c0 + lane < b;
+            const Lm<W> v = s2get(mine ? c0 + lane : a);
+            walk_leaves(v, mine, nl, hw, live);
+        }
+    }
+
     __device__ __forceinline__ void hits_unstaged(const uint64_t* rw, int row, int nl,
                                                   uint64_t (&hw)[kLeafCap / 64]) {
-        const int bw = I.bw, d = I.d;
+        const int bw = I.bw;
         int w = 0;
         uint64_t rest = uni64(rw[0]);
         int live = nl;  // l-mers without a hit yet
@@ -958,33 +938,7 @@ struct Searcher {
             __syncthreads();
             const bool mine = lane < cnt;
             const Lm<W> v = mine ? L[row * I.r + S.sv[lane]] : lm_zero<W>();
-#pragma unroll
-            for (int q = 0; q < kLeafCap / 64; q++) {
-                if (q * 64 < nl) {
-                    const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
-                    uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
-                    while (todo) {
-                        // two l-mers per round
-                        const int i0 = __builtin_ctzll(todo);
-                        todo &= todo - 1;
-                        const bool two = todo != 0ull;
-                        const int i1 = two ? __builtin_ctzll(todo) : i0;
-                        if (two) todo &= todo - 1;
-                        const Lm<W> m0 = leaf[q * 64 + i0];
-                        const Lm<W> m1 = leaf[q * 64 + i1];
-                        const unsigned long long b0 = ballot(mine && pc(dmask(m0, v)) <= d);
-                        const unsigned long long b1 = ballot(mine && pc(dmask(m1, v)) <= d);
-                        if (b0) {
-                            hw[q] |= 1ull << i0;
-                            live--;
-                        }
-                        if (two && b1) {
-                            hw[q] |= 1ull << i1;
-                            live--;
-                        }
-                    }
-                }
-            }
+            walk_leaves(v, mine, nl, hw, live);
             __syncthreads();  // S.sv is rewritten by the next chunk
         }
     }
@@ -996,88 +950,33 @@ struct Searcher {
     // one l-mer each and scan its slot's survivor bits over the segment;
     // otherwise the transposed test above on the string's level-k bitset.
     __device__ __forceinline__ void check_leaves(int k, int nl, bool staged) {
-        const int nseg = S.nseg, d = I.d, bw = I.bw;
+        const int nseg = S.nseg, bw = I.bw;
         const uint64_t* lvk = k >= 2 ? level(k) : nullptr;
         for (int g = 0; g < nseg && nl > 0; g++) {
-            int a = 0, b = 0, row = 0;
+            uint64_t hw[kLeafCap / 64];
+#pragma unroll
+            for (int q = 0; q < kLeafCap / 64; q++) hw[q] = 0ull;
             if (staged) {
-                a = S.segoff[g];
-                b = S.segoff[g + 1];
+                hits_staged(S.segoff[g], S.segoff[g + 1], nl, hw);
             } else {
-                row = S.segrow[g];
-                uint64_t hw[kLeafCap / 64];
-#pragma unroll
-                for (int q = 0; q < kLeafCap / 64; q++) hw[q] = 0ull;
+                const int row = S.segrow[g];
                 hits_unstaged(lvk + row * bw, row, nl, hw);
-                int keep_n = 0;
-#pragma unroll
-                for (int q = 0; q < kLeafCap / 64; q++) {
-                    if (q * 64 < nl) {
-                        const int i = q * 64 + lane;
-                        const bool act = i < nl;
-                        Lm<W> mv = lm_zero<W>();
-                        int sl = 0;
-                        if (act) {
-                            mv = leaf[i];
-                            sl = leafslot[i];
-                        }
-                        const bool hit = act && ((hw[q] >> lane) & 1ull);
-                        const unsigned long long hm = ballot(hit);
-                        __syncthreads();  // every lane has read its l-mer before the compaction
-                        if (hit) {
-                            const int at = keep_n + rank_below(hm);
-                            leaf[at] = mv;
-                            leafslot[at] = (uint8_t)sl;
-                        }
-                        keep_n += __popcll(hm);
-                        __syncthreads();
-                    }
-                }
-                nl = keep_n;
-                continue;
             }
+            // keep the l-mers with a hit, in order
             int keep_n = 0;
-            for (int c0 = 0; c0 < nl; c0 += 64) {
-                const int i = c0 + lane;
-                const bool act = i < nl;
-                Lm<W> mv = lm_zero<W>();
-                int sl = 0;
-                if (act) {
-                    mv = leaf[i];
-                    sl = leafslot[i];
-                }
-                bool hit = false;
-                if (act) {
-                    // up to four candidates' loads in flight per round
-                    for (int w = a >> 6; w <= (b - 1) >> 6 && !hit; w++) {
-                        uint64_t m = ~0ull;
-                        if (a - 64 * w > 0) m &= ~0ull << (a - 64 * w);
-                        if (b - 64 * w < 64) m &= (1ull << (b - 64 * w)) - 1ull;
-                        uint64_t bits = memb[sl * mw + w] & m;
-                        while (bits && !hit) {
-                            Lm<W> v[4];
-                            bool use[4];
 #pragma unroll
-                            for (int u = 0; u < 4; u++) {
-                                use[u] = bits != 0ull;
-                                const int x = use[u] ? 64 * w + __builtin_ctzll(bits) : a;
-                                bits &= bits - 1;
-                                v[u] = s2get(x);
-                            }
-#pragma unroll
-                            for (int u = 0; u < 4; u++) hit |= use[u] && pc(dmask(mv, v[u])) <= d;
-                        }
-                    }
+            for (int q = 0; q < kLeafCap / 64; q++) {
+                if (q * 64 < nl) {
+                    const int i = q * 64 + lane;
+                    const bool act = i < nl;
+                    const Lm<W> mv = act ? leaf[i] : lm_zero<W>();
+                    const bool hit = act && ((hw[q] >> lane) & 1ull);
+                    const unsigned long long hm = ballot(hit);
+                    __syncthreads();  // every lane has read its l-mer before the compaction
+                    if (hit) leaf[keep_n + rank_below(hm)] = mv;
+                    keep_n += __popcll(hm);
+                    __syncthreads();
                 }
-                const unsigned long long hm = ballot(hit);
-                __syncthreads();  // every lane has read its l-mer before the compaction
-                if (hit) {
-                    const int at = keep_n + rank_below(hm);
-                    leaf[at] = mv;
-                    leafslot[at] = (uint8_t)sl;
-                }
-                keep_n += __popcll(hm);
-                __syncthreads();
             }
             nl = keep_n;
         }
@@ -1295,11 +1194,7 @@ struct Searcher {
                 if (nz == 0ull) has = false;
             }
             const unsigned long long lm = ballot(isleaf);
-            if (isleaf) {
-                const int at = nl + rank_below(lm);
-                leaf[at] = v;
-                leafslot[at] = (uint8_t)slot;
-            }
+            if (isleaf) leaf[nl + rank_below(lm)] = v;
             nl += __popcll(lm);
             const bool done = ballot(has) == 0ull && next >= units;
             if (nl > kLeafCap - 64 || (done && nl > 0)) {
@@ -1318,14 +1213,8 @@ struct Searcher {
     __device__ __forceinline__ void tail(int k, int p, int ra, int rb) {
         const uint32_t vrows = p >= 0 ? (S.rows[k] & ~(1u << p)) : S.rows[k];
         const bool staged = stage_rows(k, vrows);
-        const int tot = S.segoff[S.nseg];
         if (p < 0) {
             if (lane == 0) ut[0] = S.st[k - 1];
-            if (staged)
-                for (int w = lane; w < mw; w += 64) {
-                    const int hi = tot - 64 * w;
-                    memb[w] = hi >= 64 ? ~0ull : hi > 0 ? (1ull << hi) - 1ull : 0ull;
-                }
             __syncthreads();
             ra = 0;
             rb = 1;
@@ -1339,12 +1228,7 @@ struct Searcher {
                 if (T <= 0) break;
                 if (lane < T) ut[lane] = L[p * I.r + S.xs[lane]];
                 __syncthreads();
-                alive = 0;
-                for (int s = 0; s < T; s++) {
-                    const bool ok = (!staged || S.nseg == 0) ? true : filter_slot(k, s, tot);
-                    if (ok) alive |= 1u << s;
-                }
-                if (staged && S.nseg > 0) __syncthreads();
+                alive = (1u << T) - 1u;
             }
             tail_generate(k, p >= 0 ? k + 1 : k, alive, staged);
             if (T < b - a) break;
@@ -1388,13 +1272,10 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
     DeepItem* ddst = (phase < 2 || (phase & 1)) ? deep0 : deep1;     // next deep phase
     QueueCounters* qd = qs + ((phase < 2 || (phase & 1)) ? 2 : 3);
     const bool deep_ok = (phase < 2 ? 2 : phase + 1) <= last_phase;
-    const int mw = (W == 1 ? 2 : 1) * s2cap / 64;  // survivor-bit words per slot
     Lm<W>* s2 = reinterpret_cast<Lm<W>*>(dyn + lv_words);
-    uint64_t* memb = reinterpret_cast<uint64_t*>(s2 + s2cap);
-    Lm<W>* ut = reinterpret_cast<Lm<W>*>(memb + kTailSlots * mw);
+    Lm<W>* ut = s2 + s2cap;
     Lm<W>* leaf = ut + kTailSlots;
-    uint8_t* leafslot = reinterpret_cast<uint8_t*>(leaf + kLeafCap);
-    uint32_t* cm = W == 3 ? reinterpret_cast<uint32_t*>(leafslot + kLeafCap) : nullptr;
+    uint32_t* cm = W == 3 ? reinterpret_cast<uint32_t*>(leaf + kLeafCap) : nullptr;
     for (;;) {
         if (lane == 0) {
             unsigned long long it = atomicAdd(&q->item_next, 1ull);
@@ -1430,7 +1311,7 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
         Searcher<W, TMAX> sr{S, dyn, level_words, I, inst, lmers + I.lmer_off,
                              compat + I.compat_off, (uint64_t)u1, keys, ctr, lane, cntw,
                              I.bw > 1 ? (uint32_t)((0xFFFFFFFFull + (uint64_t)I.bw) / (uint64_t)I.bw) : 0u,
-                             s2, memb, ut, leaf, leafslot, s2cap, mw, W == 1 && I.l <= 16,
+                             s2, ut, leaf, s2cap, W == 1 && I.l <= 16,
                              (W == 1 && I.l <= 16) ? 2 * s2cap : s2cap, cm};
         if (lane == 0) {
             S.st[0] = sr.L[u1];
@@ -1761,9 +1642,7 @@ size_t search_lds_bytes(const LaunchPlan& p) {
     // levels 2 .. max(2, t-1): the last member never gets a level of its own
     // (the tail batch replaces that push)
     const size_t lv = (size_t)(p.tmax > 3 ? p.tmax - 2 : 1) * (size_t)p.level_words * 8u;
-    const size_t mw = (size_t)(p.words == 1 ? 2 : 1) * (size_t)(p.s2cap / 64);
-    const size_t tail = (size_t)p.s2cap * lm + (size_t)kTailSlots * mw * 8u +
-                        (size_t)kTailSlots * lm + (size_t)kLeafCap * lm + (size_t)kLeafCap;
+    const size_t tail = (size_t)p.s2cap * lm + (size_t)kTailSlots * lm + (size_t)kLeafCap * lm;
     const size_t kids = p.words == 3 ? (size_t)32 * 64 * 4 : 0;  // child masks per depth and lane
     return lv + tail + kids;
 }
