@@ -111,7 +111,7 @@ typedef struct pms_tune {
                                end beyond the last window is clamped;
                                begin > end (end > 0) is PMS_E_INVAL */
     int32_t stage_cap;      /* survivors of the remaining strings staged in LDS
-                               for one tail batch (512..4096, rounded up to a
+                               for one tail batch (256..4096, rounded up to a
                                multiple of 64; 0 = by the batch's sizes);
                                larger sets are checked from the level bitsets */
     int32_t compat_mode;    /* 1: the whole compat bit-matrix; 2: only the rows

@@ -17,7 +17,8 @@ constexpr int kMaxLWide = 32;    // motif length over larger alphabets (five 32-
 constexpr int kMaxAlpha = 32;    // letters (5-bit codes)
 constexpr int kMaxT = 8;         // stack size at which generation starts
 constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
-constexpr int kStageCapMin = 512;   // staged survivors of one tail batch (LDS entries)
+constexpr int kStageCapMin = 256;   // staged survivors of one tail batch (LDS entries; also
+                                    // the push filter's listing scratch)
 constexpr int kStageCapMax = 4096;
 constexpr int kMaxInst = (1 << 20) - 1;  // instances per batch (20-bit field of a work item)
 

@@ -338,7 +338,6 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
 
 constexpr int kTailSlots = 16;  // candidates of one tail batch (<= 32: one bit each)
 constexpr int kLeafCap = 256;   // generated l-mers awaiting the check
-constexpr int kListCap = 512;   // filter listing entries per pass (lives in the staging area)
 constexpr long long kStepLimit = 1ll << 32;  // guard on every loop of the tail batch
 
 template <int W, int TMAX>
@@ -474,7 +473,7 @@ struct Searcher {
 
     // Lanes over the row words of the remaining strings: child = parent AND
     // compat(top).  With the Theorem 1 filter, the set bits of each block of
-    // 64 words are listed in LDS (kListCap entries per pass: l-mer index and
+    // 64 words are listed in LDS (s2cap entries per pass: l-mer index and
     // word/bit) by a wave prefix sum, lanes then test one listed survivor
     // each (independent l-mer loads) and clear the failures with an LDS
     // atomic AND.  Counts are taken afterwards.
@@ -510,11 +509,11 @@ struct Searcher {
             const int incl = wave_incl_scan(c);
             const int T = __shfl(incl, 63, 64);
             const int w = i - j * bw;
-            for (int lo = 0; lo < T; lo += kListCap) {
-                // list the bits of rank [lo, lo + kListCap) of this block
+            for (int lo = 0; lo < T; lo += s2cap) {
+                // list the bits of rank [lo, lo + s2cap) of this block
                 int rank = incl - c;
                 uint64_t bits = nb;
-                while (bits && rank < lo + kListCap) {
+                while (bits && rank < lo + s2cap) {
                     const int bb = __builtin_ctzll(bits);
                     bits &= bits - 1;
                     if (rank >= lo) {
@@ -524,7 +523,7 @@ struct Searcher {
                     rank++;
                 }
                 __syncthreads();
-                const int cnt = T - lo < kListCap ? T - lo : kListCap;
+                const int cnt = T - lo < s2cap ? T - lo : s2cap;
                 // four listed survivors per lane per round: their l-mer loads
                 // are independent and in flight together
                 for (int q0 = 0; q0 < cnt; q0 += 256) {
