@@ -150,7 +150,8 @@ int pms_solve(const char* const* seqs, int32_t n, int32_t m, const char* alphabe
 /* Solve `count` instances of any mix of (l, d, n, m) in one device pass: one
  * pack launch, one compat launch, a persistent search fed by a device work
  * queue (two launches: the level-2 work items, then the parts of items too
- * large for one wave), one sort/unique launch, all enqueued back to back on
+ * large for one wave; plus one per deeper stack level of split work when a
+ * threshold exceeds 3), one sort/unique launch, all enqueued back to back on
  * hip_stream (NULL = a stream of the library's own).  outs[i] receives
  * instance i's set.  tune may be NULL (the autotuner's cached setting for
  * this shape of batch, else the defaults).  At most 2^20 - 1 instances per call
