@@ -124,7 +124,8 @@ typedef struct pms_tune {
                                number of motifs (pms_expected_motifs) + 64,
                                rounded up to a power of two, at most 2^23; an
                                instance that emits more is solved again alone
-                               with room for all it emitted */
+                               with room for all it emitted.  At most 2^30
+                               (PMS_E_INVAL beyond) */
 } pms_tune;
 
 /* Autotuner.  Times the device pipeline on an evenly spread sample of at

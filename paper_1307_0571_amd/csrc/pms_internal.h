@@ -110,6 +110,8 @@ struct LaunchPlan {
     int s2cap;           // staged survivors per tail batch (multiple of 64)
     int deep_phases;     // search launches for deep items (tmax - 3, at least 0)
     unsigned long long deep_cap;  // deep items per queue
+    int sort_cands;      // instances whose key area exceeds one LDS sort chunk (multi-block sort)
+    long long sort_pmax; // the largest key area among them (a power of two)
 };
 
 // Device buffers of one planned batch.
@@ -125,6 +127,9 @@ struct DevBufs {
     InstCounters* ctr;
     QueueCounters* q;    // kQueues counter sets
     DeepItem* deep[2];   // deep-item queues
+    void* sort_cand;     // multi-block sort: candidate list, compaction scratch, chunk records
+    uint64_t* sort_tmp;
+    uint64_t* sort_side;
 };
 
 // Kernel launchers (pms_kernels.hip).  All enqueue on `stream`.
@@ -136,6 +141,10 @@ hipError_t launch_expand(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
 hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream);
 size_t search_lds_bytes(const LaunchPlan& p);
+// Multi-block sort candidate records (pms_kernels.hip).
+size_t sort_cand_bytes();
+void sort_cand_fill(void* dst, int i, int inst, long long tmp_off, long long side_off);
+constexpr int sort_chunk_keys(int kwords) { return 4096 / kwords; }
 size_t lmer_bytes(int words);
 
 // Memory plan bounds (pms_runtime.cpp): a batch needs at most

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "pms_internal.h"
 
 namespace pms {
@@ -1452,7 +1454,9 @@ __global__ __launch_bounds__(64) void k_search(const InstDev* __restrict__ insts
 
 // ---------------------------------------------------------- sort / unique (a8)
 // One block per instance: bitonic sort of the emitted keys (LDS when they fit,
-// else in place in HBM), then drop repeats with a block prefix sum.
+// else in place in HBM), then drop repeats with a block prefix sum.  With a
+// sort scratch planned, instances with more keys than one LDS chunk are left
+// to the multi-block sort below instead.
 
 template <int KW> struct Key { uint64_t w[KW]; };
 template <int KW>
@@ -1540,7 +1544,7 @@ __device__ __forceinline__ int unique_into(A a, int n, Key<KW>* g, int* scan) {
 template <int KW>
 __global__ __launch_bounds__(kSortThreads) void k_sort(const InstDev* __restrict__ insts,
                                                        uint64_t* __restrict__ keys,
-                                                       InstCounters* __restrict__ ctr) {
+                                                       InstCounters* __restrict__ ctr, int multi) {
     constexpr int kLdsKeys = 4096 / KW;
     __shared__ Key<KW> sk[kLdsKeys];
     __shared__ int scan[kSortThreads / 64 + 1];
@@ -1552,6 +1556,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const InstDev* __restrict
     if (n == 0) return;
     int P = 1;
     while (P < n) P <<= 1;
+    if (multi && P > kLdsKeys) return;
     Key<KW>* g = reinterpret_cast<Key<KW>*>(keys + I.out_off * KW);
     int written;
     if (P <= kLdsKeys) {
@@ -1577,6 +1582,266 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(const InstDev* __restrict
         written = unique_into<KW>(HbmKeys<KW>{g}, n, g, scan);
     }
     if (threadIdx.x == 0) ctr[inst].uniq = (unsigned long long)written;
+}
+
+// Multi-block sort of the instances with more emitted keys than one LDS
+// chunk (C = 4096 / KW keys): a bitonic network over P = 2^k >= n keys
+// (padding slots n .. P-1 of the instance's key area hold the largest
+// key), whose stages with a stride of at least C run as passes over HBM and
+// whose other stages run per chunk in LDS; the last merge also records each
+// chunk's distinct-key count and end keys, a scan turns them into output
+// offsets, and the distinct keys are compacted into the sort scratch and
+// copied back.  Every kernel walks the candidate list (the instances whose
+// key area exceeds C); instances that emitted at most C keys, or whose
+// network is shorter than a pass's size, skip it.
+
+struct SortCand {
+    int32_t inst;
+    int32_t pad;
+    int64_t tmp_off;   // u64 offset of its compaction area in the sort scratch
+    int64_t side_off;  // u64 offset of its per-chunk records
+};
+
+template <int KW> struct SortCtx {
+    int n, P, chunks;
+    Key<KW>* g;
+    Key<KW>* tmp;
+    Key<KW>* first;  // [chunks] smallest key of each chunk after the last merge
+    Key<KW>* last;   // [chunks] largest
+    uint64_t* co;    // [chunks] distinct count (low 32 bits), output offset (high 32)
+};
+
+template <int KW>
+__device__ __forceinline__ bool sort_ctx(const InstDev* insts, const InstCounters* ctr,
+                                         uint64_t* keys, uint64_t* tmp, uint64_t* side,
+                                         const SortCand& c, SortCtx<KW>& x) {
+    constexpr int C = 4096 / KW;
+    const InstDev I = insts[c.inst];
+    const unsigned long long cnt = ctr[c.inst].out_count;
+    if (cnt > (unsigned long long)I.out_cap || (ctr[c.inst].flags & kFlagOutOverflow)) return false;
+    if (cnt <= (unsigned long long)C) return false;
+    x.n = (int)cnt;
+    x.P = 1;
+    while (x.P < x.n) x.P <<= 1;
+    x.chunks = x.P / C;
+    x.g = reinterpret_cast<Key<KW>*>(keys + I.out_off * KW);
+    x.tmp = reinterpret_cast<Key<KW>*>(tmp + c.tmp_off);
+    x.first = reinterpret_cast<Key<KW>*>(side + c.side_off);
+    x.last = x.first + x.chunks;
+    x.co = reinterpret_cast<uint64_t*>(x.last + x.chunks);
+    return true;
+}
+
+// stages of sizes 2 .. C of every chunk, the padding written first
+template <int KW>
+__global__ __launch_bounds__(kSortThreads) void k_msort_local(const InstDev* __restrict__ insts,
+                                                              const InstCounters* __restrict__ ctr,
+                                                              uint64_t* __restrict__ keys,
+                                                              uint64_t* __restrict__ tmp,
+                                                              uint64_t* __restrict__ side,
+                                                              const SortCand* __restrict__ cand) {
+    constexpr int C = 4096 / KW;
+    __shared__ Key<KW> sk[C];
+    SortCtx<KW> x;
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, cand[blockIdx.y], x)) return;
+    for (int ch = blockIdx.x; ch < x.chunks; ch += gridDim.x) {
+        const int base = ch * C;
+        for (int i = threadIdx.x; i < C; i += kSortThreads) {
+            if (base + i < x.n) {
+                sk[i] = x.g[base + i];
+            } else {
+#pragma unroll
+                for (int w = 0; w < KW; w++) sk[i].w[w] = ~0ull;
+            }
+        }
+        __syncthreads();
+        for (int size = 2; size <= C; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int j = threadIdx.x; j < C / 2; j += kSortThreads) {
+                    const int lo = 2 * j - (j & (stride - 1));
+                    const bool up = ((base + lo) & size) == 0;
+                    const Key<KW> a = sk[lo], b = sk[lo + stride];
+                    if (key_less(b, a) == up) {
+                        sk[lo] = b;
+                        sk[lo + stride] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < C; i += kSortThreads) x.g[base + i] = sk[i];
+        __syncthreads();
+    }
+}
+
+// one stage (size, stride >= C) over HBM
+template <int KW>
+__global__ __launch_bounds__(256) void k_msort_global(const InstDev* __restrict__ insts,
+                                                      const InstCounters* __restrict__ ctr,
+                                                      uint64_t* __restrict__ keys,
+                                                      uint64_t* __restrict__ tmp,
+                                                      uint64_t* __restrict__ side,
+                                                      const SortCand* __restrict__ cand, int size,
+                                                      int stride) {
+    SortCtx<KW> x;
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, cand[blockIdx.y], x)) return;
+    if (size > x.P) return;
+    const int half = x.P / 2;
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < half; j += gridDim.x * 256) {
+        const int lo = 2 * j - (j & (stride - 1));
+        const bool up = (lo & size) == 0;
+        const Key<KW> a = x.g[lo], b = x.g[lo + stride];
+        if (key_less(b, a) == up) {
+            x.g[lo] = b;
+            x.g[lo + stride] = a;
+        }
+    }
+}
+
+// the stages of strides C/2 .. 1 of size `size` per chunk; after the last
+// merge (size == P) each chunk's distinct count and end keys
+template <int KW>
+__global__ __launch_bounds__(kSortThreads) void k_msort_merge(const InstDev* __restrict__ insts,
+                                                              const InstCounters* __restrict__ ctr,
+                                                              uint64_t* __restrict__ keys,
+                                                              uint64_t* __restrict__ tmp,
+                                                              uint64_t* __restrict__ side,
+                                                              const SortCand* __restrict__ cand,
+                                                              int size) {
+    constexpr int C = 4096 / KW;
+    __shared__ Key<KW> sk[C];
+    __shared__ int red[kSortThreads / 64];
+    SortCtx<KW> x;
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, cand[blockIdx.y], x)) return;
+    if (size > x.P) return;
+    const bool final_merge = size == x.P;
+    for (int ch = blockIdx.x; ch < x.chunks; ch += gridDim.x) {
+        const int base = ch * C;
+        for (int i = threadIdx.x; i < C; i += kSortThreads) sk[i] = x.g[base + i];
+        __syncthreads();
+        for (int stride = C >> 1; stride > 0; stride >>= 1) {
+            for (int j = threadIdx.x; j < C / 2; j += kSortThreads) {
+                const int lo = 2 * j - (j & (stride - 1));
+                const bool up = ((base + lo) & size) == 0;
+                const Key<KW> a = sk[lo], b = sk[lo + stride];
+                if (key_less(b, a) == up) {
+                    sk[lo] = b;
+                    sk[lo + stride] = a;
+                }
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < C; i += kSortThreads) x.g[base + i] = sk[i];
+        if (final_merge) {
+            // keys at positions < n only; the chunk's first key counts for now
+            int c = 0;
+            for (int i = threadIdx.x; i < C; i += kSortThreads)
+                c += (base + i < x.n && (i == 0 || !key_eq(sk[i], sk[i - 1]))) ? 1 : 0;
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int t = 0;
+                for (int w = 0; w < kSortThreads / 64; w++) t += red[w];
+                x.co[ch] = (uint64_t)(uint32_t)t;
+                x.first[ch] = sk[0];
+                const int in_chunk = x.n - base < C ? x.n - base : C;
+                x.last[ch] = sk[in_chunk > 0 ? in_chunk - 1 : 0];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// per candidate: drop the chunk-initial repeats, exclusive scan of the
+// chunk counts into output offsets, the distinct total
+template <int KW>
+__global__ __launch_bounds__(64) void k_msort_scan(const InstDev* __restrict__ insts,
+                                                   InstCounters* __restrict__ ctr,
+                                                   uint64_t* __restrict__ keys,
+                                                   uint64_t* __restrict__ tmp,
+                                                   uint64_t* __restrict__ side,
+                                                   const SortCand* __restrict__ cand) {
+    SortCtx<KW> x;
+    const SortCand c = cand[blockIdx.x];
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, c, x)) return;
+    const int lane = lane_id();
+    unsigned long long run = 0;
+    for (int c0 = 0; c0 < x.chunks; c0 += 64) {
+        const int ch = c0 + lane;
+        int cnt = 0;
+        if (ch < x.chunks && ch * (4096 / KW) < x.n) {
+            cnt = (int)(uint32_t)x.co[ch];
+            if (ch > 0 && key_eq(x.first[ch], x.last[ch - 1])) cnt--;
+        }
+        const int incl = wave_incl_scan(cnt);
+        if (ch < x.chunks)
+            x.co[ch] = (uint64_t)(uint32_t)cnt | ((uint64_t)(run + (unsigned long long)(incl - cnt)) << 32);
+        run += (unsigned long long)__shfl(incl, 63, 64);
+    }
+    if (lane == 0) ctr[c.inst].uniq = run;
+}
+
+// distinct keys of every chunk into the scratch at the chunk's offset
+template <int KW>
+__global__ __launch_bounds__(kSortThreads) void k_msort_compact(const InstDev* __restrict__ insts,
+                                                                const InstCounters* __restrict__ ctr,
+                                                                uint64_t* __restrict__ keys,
+                                                                uint64_t* __restrict__ tmp,
+                                                                uint64_t* __restrict__ side,
+                                                                const SortCand* __restrict__ cand) {
+    constexpr int C = 4096 / KW;
+    __shared__ int scan[kSortThreads / 64 + 1];
+    SortCtx<KW> x;
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, cand[blockIdx.y], x)) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int ch = blockIdx.x; ch < x.chunks; ch += gridDim.x) {
+        const int base = ch * C;
+        int written = (int)(x.co[ch] >> 32);
+        for (int c0 = 0; c0 < C; c0 += kSortThreads) {
+            const int i = base + c0 + threadIdx.x;
+            Key<KW> v;
+#pragma unroll
+            for (int w = 0; w < KW; w++) v.w[w] = 0ull;
+            bool keep = false;
+            if (i < x.n) {
+                v = x.g[i];
+                keep = i == 0 || !key_eq(v, i == base ? x.last[ch - 1] : x.g[i - 1]);
+            }
+            const unsigned long long bm = ballot(keep);
+            if (lane == 0) scan[wid] = __popcll(bm);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int acc = 0;
+                for (int q = 0; q < kSortThreads / 64; q++) {
+                    const int t = scan[q];
+                    scan[q] = acc;
+                    acc += t;
+                }
+                scan[kSortThreads / 64] = acc;
+            }
+            __syncthreads();
+            if (keep) x.tmp[written + scan[wid] + rank_below(bm)] = v;
+            written += scan[kSortThreads / 64];
+            __syncthreads();
+        }
+    }
+}
+
+// the distinct keys back to the instance's key area
+template <int KW>
+__global__ __launch_bounds__(256) void k_msort_copy(const InstDev* __restrict__ insts,
+                                                    const InstCounters* __restrict__ ctr,
+                                                    uint64_t* __restrict__ keys,
+                                                    uint64_t* __restrict__ tmp,
+                                                    uint64_t* __restrict__ side,
+                                                    const SortCand* __restrict__ cand) {
+    SortCtx<KW> x;
+    const SortCand c = cand[blockIdx.y];
+    if (!sort_ctx<KW>(insts, ctr, keys, tmp, side, c, x)) return;
+    const long long u = (long long)ctr[c.inst].uniq;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < u; i += (long long)gridDim.x * 256)
+        x.g[i] = x.tmp[i];
 }
 
 // ------------------------------------------------------------- launchers
@@ -1685,14 +1950,70 @@ hipError_t launch_search(const LaunchPlan& p, const DevBufs& b, hipStream_t stre
                         : search_w<3>(p, b, stream);
 }
 
+template <int KW>
+static hipError_t sort_kw(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
+    constexpr int C = 4096 / KW;
+    const int multi = p.sort_cands > 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_sort<KW>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
+                       b.ctr, multi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !multi) return e;
+    const SortCand* cand = reinterpret_cast<const SortCand*>(b.sort_cand);
+    for (int c0 = 0; c0 < p.sort_cands; c0 += 65535) {
+        const int nc = p.sort_cands - c0 < 65535 ? p.sort_cands - c0 : 65535;
+        const SortCand* cc = cand + c0;
+        const long long maxP = (long long)p.sort_pmax;
+        const unsigned chunk_blocks = (unsigned)std::min<long long>(maxP / C, 256);
+        const unsigned pair_blocks = (unsigned)std::min<long long>(maxP / 2 / 256, 1024);
+        hipLaunchKernelGGL(k_msort_local<KW>, dim3(chunk_blocks, nc), dim3(kSortThreads), 0, stream,
+                           b.inst, b.ctr, b.keys, b.sort_tmp, b.sort_side, cc);
+        e = hipGetLastError();
+        for (long long size = 2 * C; e == hipSuccess && size <= maxP; size <<= 1) {
+            for (long long stride = size / 2; e == hipSuccess && stride >= C; stride >>= 1) {
+                hipLaunchKernelGGL(k_msort_global<KW>, dim3(pair_blocks, nc), dim3(256), 0, stream,
+                                   b.inst, b.ctr, b.keys, b.sort_tmp, b.sort_side, cc, (int)size,
+                                   (int)stride);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_msort_merge<KW>, dim3(chunk_blocks, nc), dim3(kSortThreads), 0,
+                                   stream, b.inst, b.ctr, b.keys, b.sort_tmp, b.sort_side, cc,
+                                   (int)size);
+                e = hipGetLastError();
+            }
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_msort_scan<KW>, dim3(nc), dim3(64), 0, stream, b.inst, b.ctr,
+                               b.keys, b.sort_tmp, b.sort_side, cc);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_msort_compact<KW>, dim3(chunk_blocks, nc), dim3(kSortThreads), 0,
+                               stream, b.inst, b.ctr, b.keys, b.sort_tmp, b.sort_side, cc);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_msort_copy<KW>, dim3(pair_blocks, nc), dim3(256), 0, stream, b.inst,
+                               b.ctr, b.keys, b.sort_tmp, b.sort_side, cc);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_sort(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
-    if (p.kwords == 1)
-        hipLaunchKernelGGL(k_sort<1>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
-                           b.ctr);
-    else
-        hipLaunchKernelGGL(k_sort<2>, dim3(p.n_inst), dim3(kSortThreads), 0, stream, b.inst, b.keys,
-                           b.ctr);
-    return hipGetLastError();
+    return p.kwords == 1 ? sort_kw<1>(p, b, stream) : sort_kw<2>(p, b, stream);
+}
+
+size_t sort_cand_bytes() { return sizeof(SortCand); }
+
+void sort_cand_fill(void* dst, int i, int inst, long long tmp_off, long long side_off) {
+    SortCand c{};
+    c.inst = inst;
+    c.tmp_off = tmp_off;
+    c.side_off = side_off;
+    reinterpret_cast<SortCand*>(dst)[i] = c;
 }
 
 }  // namespace pms

@@ -261,6 +261,7 @@ struct pms_batch {
     int failed = PMS_OK;  // sticky error: the batch's device state is unusable
     int words = 1;   // l-mer class (1, 2, or 3 for alphabets of more than 4 letters)
     int kwords = 1;  // u64 words per key
+    std::vector<uint8_t> sort_cands;     // multi-block sort candidate records (uploaded)
     std::vector<InstCounters> last_ctr;  // counters read back by the last results call
 };
 
@@ -363,6 +364,28 @@ size_t plan_layout(pms_batch* bt) {
     size_t o_deep0 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
     size_t o_deep1 = take((int64_t)p.deep_cap * (int64_t)sizeof(DeepItem));
     size_t o_keys = take(out_off * 8 * bt->kwords);
+    // multi-block sort: instances whose key area exceeds one LDS chunk get a
+    // compaction area as large as their key area and one record per chunk
+    const int64_t chunk = sort_chunk_keys(bt->kwords);
+    int ncand = 0;
+    int64_t tmp_words = 0, side_words = 0;
+    p.sort_pmax = 0;
+    for (const InstDev& d : bt->dinst)
+        if (d.out_cap > chunk) ncand++;
+    bt->sort_cands.assign((size_t)ncand * sort_cand_bytes(), 0);
+    ncand = 0;
+    for (int i = 0; i < ni; i++) {
+        const InstDev& d = bt->dinst[i];
+        if (d.out_cap <= chunk) continue;
+        sort_cand_fill(bt->sort_cands.data(), ncand++, i, tmp_words, side_words);
+        tmp_words += d.out_cap * bt->kwords;
+        side_words += (d.out_cap / chunk) * (2 * bt->kwords + 1);
+        p.sort_pmax = std::max<long long>(p.sort_pmax, d.out_cap);
+    }
+    p.sort_cands = ncand;
+    size_t o_scand = take((int64_t)bt->sort_cands.size());
+    size_t o_stmp = take(tmp_words * 8);
+    size_t o_sside = take(side_words * 8);
     size_t o_ctr = take((int64_t)ni * sizeof(InstCounters));
     size_t o_q = take(kQueues * sizeof(QueueCounters));
     // offsets are stored relative to the arena; resolve later
@@ -378,6 +401,9 @@ size_t plan_layout(pms_batch* bt) {
     bt->b.keys = (uint64_t*)o_keys;
     bt->b.ctr = (InstCounters*)o_ctr;
     bt->b.q = (QueueCounters*)o_q;
+    bt->b.sort_cand = (void*)o_scand;
+    bt->b.sort_tmp = (uint64_t*)o_stmp;
+    bt->b.sort_side = (uint64_t*)o_sside;
     return off;
 }
 
@@ -398,7 +424,9 @@ size_t inst_bytes(int n, int m, int l, int d, int sigma, const pms_tune* tune) {
     // deep-item queues exist only in batches with a threshold above 3; two
     // queues of at most 2 * (sum of r^2, at least 1024) entries
     const int64_t deep = t > 3 ? 2 * (2 * r * std::max<int64_t>(r, 1) + 2048) * (int64_t)sizeof(DeepItem) : 0;
-    return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 +
+    // keys (2 words) plus the multi-block sort's compaction area and records
+    return (size_t)((int64_t)sizeof(InstDev) + (int64_t)n * m + 256 + cap * 17 +
+                    (int64_t)sort_cand_bytes() + 256 +
                     N * (int64_t)lmer_bytes(3) + N * n * bw * 8 +
                     2 * r * std::max<int64_t>(r, 1) * 8 + cap * 16 + (int64_t)sizeof(InstCounters) +
                     deep);
@@ -430,6 +458,9 @@ void resolve(pms_batch* bt) {
     bt->b.keys = (uint64_t*)(a + (size_t)bt->b.keys);
     bt->b.ctr = (InstCounters*)(a + (size_t)bt->b.ctr);
     bt->b.q = (QueueCounters*)(a + (size_t)bt->b.q);
+    bt->b.sort_cand = (void*)(a + (size_t)bt->b.sort_cand);
+    bt->b.sort_tmp = (uint64_t*)(a + (size_t)bt->b.sort_tmp);
+    bt->b.sort_side = (uint64_t*)(a + (size_t)bt->b.sort_side);
 }
 
 void release_arena(pms_batch* bt) {
@@ -475,6 +506,9 @@ int materialise(pms_batch* bt, bool use_cache) {
         e = hipMemcpyAsync(bt->b.chars, bt->chars.data(), bt->chars.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(bt->b.lut, bt->lut.data(), bt->lut.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !bt->sort_cands.empty())
+        e = hipMemcpyAsync(bt->b.sort_cand, bt->sort_cands.data(), bt->sort_cands.size(),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(bt->uploaded, s);
     return hip_status(e);
 }
@@ -514,7 +548,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
         if (tune->s1_begin < 0 || tune->s1_end < 0 ||
             (tune->s1_end > 0 && tune->s1_begin > tune->s1_end))
             return PMS_E_INVAL;
-        if (tune->out_capacity < 0) return PMS_E_INVAL;
+        if (tune->out_capacity < 0 || tune->out_capacity > (int64_t(1) << 30)) return PMS_E_INVAL;
         if (tune->stage_cap < 0 || tune->stage_cap > kStageCapMax) return PMS_E_INVAL;
         if (tune->compat_mode < 0 || tune->compat_mode > 2) return PMS_E_INVAL;
     }
@@ -610,6 +644,7 @@ int rerun_overflowed(pms_batch* bt, const std::vector<int>& idx,
         }
         alphas[k] = h.alpha;
         sub[k] = pms_instance{ptrs[k].data(), h.n, h.m, alphas[k].c_str(), h.l, h.d};
+        if (ctr[i].out_count > (1ull << 30)) return PMS_E_NOMEM;  // beyond the sort's index range
         caps[k] = next_pow2(std::max<int64_t>((int64_t)ctr[i].out_count, 1));
     }
     pms_tune t = bt->tune;  // same threshold, width and S_1 window range
