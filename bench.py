@@ -418,6 +418,20 @@ def serving_main(args, I, pms):
     b.results()
     capacity = len(head) / (time.perf_counter() - t0)
     b.close()
+    # the plain rate on the same requests: one device pipeline run each
+    singles = [pms.Batch([p]) for p in head]
+    for sb in singles:
+        sb.run()
+        sb.results()
+    tp = time.perf_counter()
+    for sb in singles:
+        sb.run()
+        sb.results()
+    plain_rate = len(head) / (time.perf_counter() - tp)
+    for sb in singles:
+        sb.close()
+    print(json.dumps({"capacity_instances_per_s": round(capacity, 3),
+                      "plain_instances_per_s": round(plain_rate, 3)}), flush=True)
     rate = max(1e-3, args.load * capacity)
     rng = random.Random(7)
     srv = pms.Server(workers=args.workers)
@@ -462,7 +476,10 @@ def serving_main(args, I, pms):
             print(json.dumps({"progress": i + 1, "done": len(done)}), flush=True)
     with lock:
         submitting[0] = False
-    th.join()
+    while th.is_alive():
+        th.join(timeout=30)
+        if th.is_alive():
+            print(json.dumps({"progress": len(insts), "done": len(done)}), flush=True)
     total = time.perf_counter() - t0
     srv.close()
     lat = []
@@ -474,6 +491,8 @@ def serving_main(args, I, pms):
     print(json.dumps({"workload": "serving", "requests": len(insts), "workers": args.workers,
                       "capacity_instances_per_s": capacity, "offered_rate": rate,
                       "instances_per_s": len(insts) / total,
+                      "plain_instances_per_s": plain_rate,
+                      "served_over_plain": (len(insts) / total) / plain_rate,
                       "p50_ms": 1e3 * lat[len(lat) // 2],
                       "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]}),
           flush=True)
