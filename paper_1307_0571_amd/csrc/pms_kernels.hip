@@ -355,7 +355,7 @@ struct SearchLds {
     int nseg;
     int item;
     int xs[kTailSlots];              // window of each slot's candidate
-    int sv[64];                      // windows of the survivors a transposed check holds
+    int sv[256];                     // windows of the survivors a transposed check holds
     int aslot[kTailSlots];           // live slots, in order
     Lm<W> dq_v[64];                  // donated subtrees: prefix,
     uint8_t dq_d[64], dq_s[64];      // depth and slot
@@ -863,7 +863,8 @@ struct Searcher {
     // survivors at a time (one load each) and the l-mers without a hit yet
     // are walked uniformly, each tested against all of them in one wave
     // instruction.  Bit i of hw[i / 64] is set for l-mer i with a hit.
-    __device__ __forceinline__ void walk_leaves(const Lm<W>& v, bool mine, int nl,
+    template <int V>
+    __device__ __forceinline__ void walk_leaves(const Lm<W> (&v)[V], const bool (&mine)[V], int nl,
                                                 uint64_t (&hw)[kLeafCap / 64], int& live) const {
         const int d = I.d;
 #pragma unroll
@@ -880,8 +881,14 @@ struct Searcher {
                     if (two) todo &= todo - 1;
                     const Lm<W> m0 = leaf[q * 64 + i0];
                     const Lm<W> m1 = leaf[q * 64 + i1];
-                    const unsigned long long b0 = ballot(mine && pc(dmask(m0, v)) <= d);
-                    const unsigned long long b1 = ballot(mine && pc(dmask(m1, v)) <= d);
+                    bool h0 = false, h1 = false;
+#pragma unroll
+                    for (int u = 0; u < V; u++) {
+                        h0 |= mine[u] && pc(dmask(m0, v[u])) <= d;
+                        h1 |= mine[u] && pc(dmask(m1, v[u])) <= d;
+                    }
+                    const unsigned long long b0 = ballot(h0);
+                    const unsigned long long b1 = ballot(h1);
                     if (b0) {
                         hw[q] |= 1ull << i0;
                         live--;
@@ -895,34 +902,54 @@ struct Searcher {
         }
     }
 
-    // The same for a staged segment [a, b) of the staging area.
-    __device__ __forceinline__ void hits_staged(int a, int b, int nl,
-                                                uint64_t (&hw)[kLeafCap / 64]) {
+    // Survivors a lane holds per pass (V of them, 64 V per wave), by the
+    // segment's size (V up to 4 for the 8-byte l-mers, 2 for the wider
+    // ones, whose registers would cost resident waves): each buffered
+    // l-mer's visit tests them all.
+    template <int V>
+    __device__ __forceinline__ void hits_staged_v(int a, int b, int nl,
+                                                  uint64_t (&hw)[kLeafCap / 64]) {
         int live = nl;
-        for (int c0 = a; c0 < b && live > 0; c0 += 64) {
-            const bool mine = c0 + lane < b;
-            const Lm<W> v = s2get(mine ? c0 + lane : a);
-            walk_leaves(v, mine, nl, hw, live);
+        for (int c0 = a; c0 < b && live > 0; c0 += 64 * V) {
+            Lm<W> v[V];
+            bool mine[V];
+#pragma unroll
+            for (int u = 0; u < V; u++) {
+                const int x = c0 + 64 * u + lane;
+                mine[u] = x < b;
+                v[u] = s2get(mine[u] ? x : a);
+            }
+            walk_leaves<V>(v, mine, nl, hw, live);
         }
     }
 
-    __device__ __forceinline__ void hits_unstaged(const uint64_t* rw, int row, int nl,
-                                                  uint64_t (&hw)[kLeafCap / 64]) {
+    // The same for a staged segment [a, b) of the staging area.
+    __device__ __forceinline__ void hits_staged(int a, int b, int nl,
+                                                uint64_t (&hw)[kLeafCap / 64]) {
+        const int sz = b - a;
+        if (W == 1 && sz > 128) hits_staged_v<W == 1 ? 4 : 2>(a, b, nl, hw);
+        else if (sz > 64) hits_staged_v<2>(a, b, nl, hw);
+        else hits_staged_v<1>(a, b, nl, hw);
+    }
+
+    template <int V>
+    __device__ __forceinline__ void hits_unstaged_v(const uint64_t* rw, int row, int nl,
+                                                    uint64_t (&hw)[kLeafCap / 64]) {
         const int bw = I.bw;
         int w = 0;
         uint64_t rest = uni64(rw[0]);
         int live = nl;  // l-mers without a hit yet
         while (live > 0) {
-            // the next (up to) 64 survivors, in window order, into S.sv
+            // the next (up to) 64 V survivors, in window order, into S.sv
             int cnt = 0;
-            while (cnt < 64) {
+            while (cnt < 64 * V) {
                 if (rest == 0ull) {
                     if (++w >= bw) break;
                     rest = uni64(rw[w]);
                     continue;
                 }
                 const int pcnt = __popcll(rest);
-                const int take = pcnt < 64 - cnt ? pcnt : 64 - cnt;
+                const int take = pcnt < 64 * V - cnt ? pcnt : 64 * V - cnt;
                 const bool set = (rest >> lane) & 1ull;
                 const int rk = rank_below(rest);
                 if (set && rk < take) S.sv[cnt + rk] = w * 64 + lane;
@@ -937,19 +964,30 @@ struct Searcher {
             }
             if (cnt == 0) break;
             __syncthreads();
-            const bool mine = lane < cnt;
-            const Lm<W> v = mine ? L[row * I.r + S.sv[lane]] : lm_zero<W>();
-            walk_leaves(v, mine, nl, hw, live);
-            __syncthreads();  // S.sv is rewritten by the next chunk
+            Lm<W> v[V];
+            bool mine[V];
+#pragma unroll
+            for (int u = 0; u < V; u++) {
+                mine[u] = 64 * u + lane < cnt;
+                v[u] = mine[u] ? L[row * I.r + S.sv[64 * u + lane]] : lm_zero<W>();
+            }
+            walk_leaves<V>(v, mine, nl, hw, live);
+            __syncthreads();  // S.sv is rewritten by the next pass
         }
+    }
+
+    __device__ __forceinline__ void hits_unstaged(const uint64_t* rw, int row, int nl, int sz,
+                                                  uint64_t (&hw)[kLeafCap / 64]) {
+        if (W == 1 && sz > 128) hits_unstaged_v<W == 1 ? 4 : 2>(rw, row, nl, hw);
+        else if (sz > 64) hits_unstaged_v<2>(rw, row, nl, hw);
+        else hits_unstaged_v<1>(rw, row, nl, hw);
     }
 
     // Check the buffered l-mers against every remaining string, one string
     // (segment) at a time, fewest survivors first; the l-mers that have a
     // survivor of that string within d are compacted in place and go on to
-    // the next string, the rest are motifs.  Staged survivors: lanes take
-    // one l-mer each and scan its slot's survivor bits over the segment;
-    // otherwise the transposed test above on the string's level-k bitset.
+    // the next string, the rest are motifs.  The survivors come from the
+    // staging area, or from the string's level-k bitset when not staged.
     __device__ __forceinline__ void check_leaves(int k, int nl, bool staged) {
         const int nseg = S.nseg, bw = I.bw;
         const uint64_t* lvk = k >= 2 ? level(k) : nullptr;
@@ -961,7 +999,7 @@ struct Searcher {
                 hits_staged(S.segoff[g], S.segoff[g + 1], nl, hw);
             } else {
                 const int row = S.segrow[g];
-                hits_unstaged(lvk + row * bw, row, nl, hw);
+                hits_unstaged(lvk + row * bw, row, nl, (int)cnt16(k, row), hw);
             }
             // keep the l-mers with a hit, in order
             int keep_n = 0;
