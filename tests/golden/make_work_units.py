@@ -9,8 +9,8 @@ work_units_batched.json  the 256-instance mixed batch: counts on a run of 16
                          seeded uniform position (the independent
                          sub-problems of Section 2.3, so the counts of a
                          window set add up; every window is equally likely
-                         to be counted), scaled by r / 16, at t = 2, 3
-                         and 4 (the benchmark picks the t the device ran).
+                         to be counted), scaled by r / 16, at t = 2 and
+                         t = 3 (the benchmark picks the t the device ran).
 
 Usage: python tests/golden/make_work_units.py [plain] [batched] [--threads N]
 Calls only the oracle and the seeded instance generator.
@@ -68,7 +68,7 @@ def batched(threads):
         e = {"index": k, "seed": x.seed, "l": x.l, "d": x.d, "n": x.n, "m": x.m,
              "windows": [w0, w1], "by_t": {}}
         t0 = time.time()
-        for t in (2, 3, 4):
+        for t in (2, 3):
             _, st = oracle.solve_b(x.seqs, x.l, x.d, t=t, stats=True, threads=threads,
                                    windows=(w0, w1))
             e["by_t"][str(t)] = {u: st[u] * r / (w1 - w0) for u in UNITS}
