@@ -518,7 +518,7 @@ def main():
     ap.add_argument("--stage-cap", type=int, default=0, help="staged survivors per tail batch")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched: use the flags / defaults instead of pms_autotune")
-    ap.add_argument("--tune-runs", type=int, default=16, help="autotuner pipeline runs")
+    ap.add_argument("--tune-runs", type=int, default=24, help="autotuner pipeline runs")
     ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--workers", type=int, default=3, help="serving: overlapping passes")
     ap.add_argument("--load", type=float, default=0.7,

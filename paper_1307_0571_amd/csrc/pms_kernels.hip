@@ -356,6 +356,7 @@ struct SearchLds {
     int item;
     int xs[kTailSlots];              // window of each slot's candidate
     int sv[256];                     // windows of the survivors a transposed check holds
+    int lix[64];                     // l-mers a grouped check round takes, by group
     int aslot[kTailSlots];           // live slots, in order
     Lm<W> dq_v[64];                  // donated subtrees: prefix,
     uint8_t dq_d[64], dq_s[64];      // depth and slot
@@ -902,6 +903,43 @@ struct Searcher {
         }
     }
 
+    // Segments of at most 8 survivors: the wave splits into 64 / C groups of
+    // C lanes (C the survivor count rounded up to a power of two), lane x of
+    // every group holds survivor x, and each group tests a different
+    // buffered l-mer, so one round takes 64 / C l-mers.
+    __device__ __forceinline__ void walk_grouped(const Lm<W>& v, bool mine, int C, int nl,
+                                                 uint64_t (&hw)[kLeafCap / 64], int& live) {
+        const int d = I.d;
+        const int G = 64 / C;
+        const int j = lane / C;
+        const unsigned long long cmask = C >= 64 ? ~0ull : ((1ull << C) - 1ull);
+#pragma unroll
+        for (int q = 0; q < kLeafCap / 64; q++) {
+            if (q * 64 < nl) {
+                const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
+                uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
+                while (todo) {
+                    // the round's l-mers: the G lowest pending ones, one per group
+                    const bool set = (todo >> lane) & 1ull;
+                    const int rk = rank_below(todo);
+                    const bool sel = set && rk < G;
+                    if (sel) S.lix[rk] = lane;
+                    __syncthreads();
+                    const int nsel = __popcll(todo) < G ? __popcll(todo) : G;
+                    const bool act = j < nsel;
+                    const Lm<W> m = act ? leaf[q * 64 + S.lix[j]] : lm_zero<W>();
+                    const unsigned long long bm = ballot(act && mine && pc(dmask(m, v)) <= d);
+                    const bool hit = sel && ((bm >> (rk * C)) & cmask) != 0ull;
+                    const unsigned long long hb = ballot(hit);
+                    hw[q] |= hb;
+                    live -= __popcll(hb);
+                    todo &= ~ballot(sel);
+                    __syncthreads();  // S.lix is rewritten by the next round
+                }
+            }
+        }
+    }
+
     // Survivors a lane holds per pass (V of them, 64 V per wave), by the
     // segment's size (V up to 4 for the 8-byte l-mers, 2 for the wider
     // ones, whose registers would cost resident waves): each buffered
@@ -927,6 +965,16 @@ struct Searcher {
     __device__ __forceinline__ void hits_staged(int a, int b, int nl,
                                                 uint64_t (&hw)[kLeafCap / 64]) {
         const int sz = b - a;
+        if (sz <= 8) {
+            int C = 1;
+            while (C < sz) C <<= 1;
+            const int x = lane & (C - 1);
+            const bool mine = x < sz;
+            const Lm<W> v = s2get(mine ? a + x : a);
+            int live = nl;
+            walk_grouped(v, mine, C, nl, hw, live);
+            return;
+        }
         if (W == 1 && sz > 128) hits_staged_v<W == 1 ? 4 : 2>(a, b, nl, hw);
         else if (sz > 64) hits_staged_v<2>(a, b, nl, hw);
         else hits_staged_v<1>(a, b, nl, hw);
@@ -978,6 +1026,29 @@ struct Searcher {
 
     __device__ __forceinline__ void hits_unstaged(const uint64_t* rw, int row, int nl, int sz,
                                                   uint64_t (&hw)[kLeafCap / 64]) {
+        if (sz <= 8) {
+            // list the (at most 8) survivors, then the grouped walk
+            int cnt = 0;
+            for (int w = 0; w < I.bw && cnt < sz; w++) {
+                const uint64_t bits = uni64(rw[w]);
+                if (bits == 0ull) continue;
+                const bool set = (bits >> lane) & 1ull;
+                const int rk = cnt + rank_below(bits);
+                if (set && rk < 8) S.sv[rk] = w * 64 + lane;
+                cnt += __popcll(bits);
+            }
+            if (cnt > 8) cnt = 8;
+            __syncthreads();
+            int C = 1;
+            while (C < cnt) C <<= 1;
+            const int x = lane & (C - 1);
+            const bool mine = x < cnt;
+            const Lm<W> v = mine ? L[row * I.r + S.sv[x]] : lm_zero<W>();
+            int live = nl;
+            walk_grouped(v, mine, C, nl, hw, live);
+            __syncthreads();
+            return;
+        }
         if (W == 1 && sz > 128) hits_unstaged_v<W == 1 ? 4 : 2>(rw, row, nl, hw);
         else if (sz > 64) hits_unstaged_v<2>(rw, row, nl, hw);
         else hits_unstaged_v<1>(rw, row, nl, hw);
@@ -1246,6 +1317,26 @@ struct Searcher {
         __syncthreads();
     }
 
+    // Whether every staged segment has a survivor within 2d of slot s's
+    // candidate (else no l-mer of its tree can be a motif: the pair
+    // condition of Section 2.4).  Used for alphabets of more than 4 letters,
+    // where it removes many slots; on DNA nearly every slot passes.
+    __device__ __forceinline__ bool slot_alive(int s) {
+        const Lm<W> cand = ut[s];
+        const int d2 = 2 * I.d;
+        for (int g = 0; g < S.nseg; g++) {
+            const int a = S.segoff[g], b = S.segoff[g + 1];
+            bool any = false;
+            for (int c0 = a; c0 < b && !any; c0 += 64) {
+                const int x = c0 + lane;
+                const bool ok = x < b && pc(dmask(cand, s2get(x < b ? x : a))) <= d2;
+                any = ballot(ok) != 0ull;
+            }
+            if (!any) return false;
+        }
+        return true;
+    }
+
     // Tail batch.  p >= 0: the stack st[0..k) is followed by each survivor
     // of string p at level k with rank in [ra, rb).  p < 0: the stack
     // st[0..k) is complete (one slot).
@@ -1268,6 +1359,9 @@ struct Searcher {
                 if (lane < T) ut[lane] = L[p * I.r + S.xs[lane]];
                 __syncthreads();
                 alive = (1u << T) - 1u;
+                if (I.asize > 4 && staged)
+                    for (int s = 0; s < T; s++)
+                        if (!slot_alive(s)) alive &= ~(1u << s);
             }
             tail_generate(k, p >= 0 ? k + 1 : k, alive, staged);
             if (T < b - a) break;
