@@ -168,20 +168,35 @@ def run_batched(args, I, pms, insts=None):
     tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc, split=args.split,
                     stage_cap=args.stage_cap)
     default_rate = None
+    tuned_note = "flags"
     if args.autotune:
-        # the autotuner picks the search parameters on a 32-instance sample
-        # of the batch; the defaults are timed once on the whole batch beside
-        # the tuned steps
+        # the autotuner proposes search parameters from a 64-instance sample
+        # of the batch; the proposal and the defaults are each timed once on
+        # the whole batch, and the faster of the two runs the timed steps
         base = tune
-        tune = pms.autotune(probs, base=base, max_runs=args.tune_runs, sample=32)
-        b0 = pms.Batch(probs, tune=base)
-        b0.run()
-        b0.results()
-        t0 = time.perf_counter()
-        b0.run()
-        b0.results()
-        default_rate = len(probs) / (time.perf_counter() - t0)
-        b0.close()
+
+        def one_pass(t):
+            b0 = pms.Batch(probs, tune=t)
+            b0.run()
+            b0.results()
+            t0 = time.perf_counter()
+            b0.run()
+            b0.results()
+            rate = len(probs) / (time.perf_counter() - t0)
+            b0.close()
+            return rate
+
+        proposal = pms.autotune(probs, base=base, max_runs=args.tune_runs, sample=64)
+        default_rate = one_pass(base)
+        proposal_rate = one_pass(proposal)
+        if proposal_rate >= default_rate:
+            tune = proposal
+            tuned_note = (f"pms_autotune (64-instance sample); {proposal_rate:.2f} vs "
+                          f"{default_rate:.2f} instances/s with the defaults on the whole batch")
+        else:
+            tune = base
+            tuned_note = (f"defaults: pms_autotune's proposal {pms.tune_dict(proposal)} ran "
+                          f"{proposal_rate:.2f} vs {default_rate:.2f} instances/s on the whole batch")
     b = pms.Batch(probs, tune=tune)
     for _ in range(args.warmup):
         b.run()
@@ -225,11 +240,12 @@ def run_batched(args, I, pms, insts=None):
         plain = time.perf_counter() - tp
         for sb in singles:
             sb.close()
-    return insts, elapsed, phases, plain, graph_rate, [len(r) for r in res], tune, default_rate
+    return insts, elapsed, phases, plain, graph_rate, [len(r) for r in res], tune, default_rate, tuned_note
 
 
 def batched_main(args, I, pms):
-    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate = run_batched(args, I, pms)
+    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note = run_batched(
+        args, I, pms)
     n = len(insts)
     value = n * args.steps / elapsed
     t_of = [tune.threshold or pms.default_threshold(x.n, x.m, x.l, x.d) for x in insts]
@@ -278,7 +294,7 @@ def batched_main(args, I, pms):
                    "tune": {k: v for k, v in pms.tune_dict(tune).items()
                             if k in ("threshold", "lmer_words", "triple_filter", "waves_per_cu",
                                      "split", "stage_cap")},
-                   "tuned_by": "pms_autotune (32-instance sample)" if args.autotune else "flags"},
+                   "tuned_by": tuned_note},
         "default_tune_instances_per_s": round(default_rate, 3) if default_rate else None,
         "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
         "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
@@ -303,7 +319,7 @@ def protein_main(args, I, pms):
     """The batched configuration over the 20 amino acids (five-plane l-mers,
     5-bit keys): batched and plain rates and the CPU oracle beside them."""
     insts = I.batch_mix(PROTEIN_SEED0, args.count, ld=PROTEIN_LD, alphabet=I.PROTEIN)
-    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate = run_batched(
+    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note = run_batched(
         args, I, pms, insts)
     n = len(insts)
     value = n * args.steps / elapsed
@@ -312,7 +328,7 @@ def protein_main(args, I, pms):
                        f"seeds {PROTEIN_SEED0}-{PROTEIN_SEED0 + n - 1}; inputs resident in HBM",
            "instances_per_s": round(value, 3), "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
            "steps": args.steps,
-           "tune": pms.tune_dict(tune),
+           "tune": pms.tune_dict(tune), "tuned_by": tuned_note,
            "default_tune_instances_per_s": round(default_rate, 3) if default_rate else None,
            "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
            "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
