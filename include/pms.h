@@ -100,7 +100,7 @@ typedef struct pms_tune {
                                version; 2, an int8 one-hot MFMA builder, returns
                                PMS_E_UNSUPPORTED); 0 = 1 */
     int32_t split;          /* survivors of the next member's string one wave
-                               keeps (1..2047; 0 = 16); the rest are queued in
+                               keeps (1..2047; 0 = 32); the rest are queued in
                                ranges of this size for other waves: at stack
                                size 2 as part items (a second launch), at 3
                                and up as deep items (further launches) */
@@ -129,16 +129,18 @@ typedef struct pms_tune {
 } pms_tune;
 
 /* Autotuner.  Times the device pipeline on an evenly spread sample of at
- * most `sample` of the instances (0 = 32) for candidate settings --
- * staged survivors per tail batch, part size, waves per CU, threshold t
- * (which Section 2.2 and Appendix D leave to measurement), the Theorem 1
- * filter, the l-mer width -- one parameter at a time from `base` (NULL =
- * the defaults), at most max_runs pipeline runs (0 = 16), keeping a change
- * only when it is at least 2% faster, and writes the best setting to out.
- * No setting changes the motif sets; a candidate whose counts differ from
- * the base's is rejected.  The result is cached for batches of the same
- * shape (the distinct (l, d, n/8, m/256) of the instances and log2 of their
- * number), in the process and in the file PMS_TUNE_CACHE names if set;
+ * most `sample` of the instances (0 = 32) for candidate settings -- the
+ * threshold t first (which Section 2.2 and Appendix D leave to
+ * measurement), then staged survivors per tail batch, part size, waves per
+ * CU, the Theorem 1 filter, the l-mer width -- one parameter at a time from
+ * `base` (NULL = the defaults), at most max_runs pipeline runs (0 = 16),
+ * keeping a change only when it is at least 2% faster on the sample, and
+ * writes the best setting to out (a sample can mislead: time the proposal
+ * on the whole batch before relying on it).  No setting changes the motif
+ * sets; a candidate whose counts differ from the base's is rejected.  The
+ * result is cached for batches of the same shape (the distinct (l, d, n/8,
+ * m/256, alphabet size) of the instances and log2 of their number), in the
+ * process and in the file PMS_TUNE_CACHE names if set;
  * pms_solve_batch / pms_batch_create / pms_batch_workspace_size with
  * tune == NULL use it.  Blocks; uses the device. */
 int pms_autotune(const pms_instance* inst, int32_t count, const pms_tune* base, int32_t max_runs,

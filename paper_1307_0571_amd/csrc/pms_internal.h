@@ -16,7 +16,7 @@ constexpr int kMaxL = 64;        // motif length (two 64-bit bit-planes; alphabe
 constexpr int kMaxLWide = 32;    // motif length over larger alphabets (five 32-bit planes)
 constexpr int kMaxAlpha = 32;    // letters (5-bit codes)
 constexpr int kMaxT = 8;         // stack size at which generation starts
-constexpr int kSplitDefault = 16;  // third stack members one work item keeps (rest: part items)
+constexpr int kSplitDefault = 32;  // third stack members one work item keeps (rest: part items)
 constexpr int kStageCapMin = 256;   // staged survivors of one tail batch (LDS entries; also
                                     // the push filter's listing scratch)
 constexpr int kStageCapMax = 4096;

@@ -180,7 +180,7 @@ extern "C" int pms_autotune(const pms_instance* inst, int32_t count, const pms_t
     const std::vector<Dim> dims = {
         {&pms_tune::threshold, {3, 4, 2}},
         {&pms_tune::stage_cap, {256, 384, 512, 768, 1024, 2048}},
-        {&pms_tune::split, {8, 12, 24, 32}},
+        {&pms_tune::split, {16, 24, 48, 64}},
         {&pms_tune::waves_per_cu, {8, 12, 16, 24}},
         {&pms_tune::triple_filter, {-1}},
         {&pms_tune::lmer_words, {2}},
