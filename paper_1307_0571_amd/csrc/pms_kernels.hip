@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_expand(const InstDev* __restrict__ inst
             const uint64_t x2 = (uint64_t)(w * 64 + b);
             items[base + o++] = make_item((uint64_t)inst, 0, (uint64_t)u1, (uint64_t)p2, x2);
         }
-        done += __shfl(incl, 63, 64);
+        done += uni(__shfl(incl, 63, 64));
     }
 }
 
@@ -510,7 +510,7 @@ struct Searcher {
             if (!I.triple && !fly) continue;
             const int c = pc(nb);
             const int incl = wave_incl_scan(c);
-            const int T = __shfl(incl, 63, 64);
+            const int T = uni(__shfl(incl, 63, 64));
             const int w = i - j * bw;
             for (int lo = 0; lo < T; lo += s2cap) {
                 // list the bits of rank [lo, lo + s2cap) of this block
@@ -603,7 +603,7 @@ struct Searcher {
                 }
                 return __shfl(res, src, 64);
             }
-            done = __shfl(incl, 63, 64);
+            done = uni(__shfl(incl, 63, 64));
         }
         return -1;
     }
@@ -683,7 +683,7 @@ struct Searcher {
         const bool mine = lane < n && ((vrows >> lane) & 1u);
         const int c = mine ? (int)cnt16(k, lane) : 0;
         const int incl = wave_incl_scan(c);
-        const int tot = __shfl(incl, 63, 64);
+        const int tot = uni(__shfl(incl, 63, 64));
         int rank = 0;
         for (int j = 0; j < n; j++) {
             const int cj = __shfl(c, j, 64);
@@ -730,7 +730,7 @@ struct Searcher {
                 if (W == 1 && half) s2h()[o++] = (uint32_t)g;
                 else s2[o++].h = (M)g;
             }
-            done += __shfl(inc, 63, 64);
+            done += uni(__shfl(inc, 63, 64));
         }
         __syncthreads();
         // four loads in flight per lane
@@ -771,7 +771,7 @@ struct Searcher {
                 if (rank >= a) S.xs[rank - a] = (w0 + lane) * 64 + bb;
                 rank++;
             }
-            done = __shfl(incl, 63, 64);
+            done = uni(__shfl(incl, 63, 64));
         }
         __syncthreads();
         const int hi = b < done ? b : done;
@@ -872,7 +872,9 @@ struct Searcher {
         for (int q = 0; q < kLeafCap / 64; q++) {
             if (q * 64 < nl) {
                 const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
-                uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
+                // the loop state is wave-uniform: keep it in scalar registers
+                uint64_t todo = uni64(~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull)));
+                uint64_t hit = 0ull;
                 while (todo) {
                     // two l-mers per round
                     const int i0 = __builtin_ctzll(todo);
@@ -888,17 +890,12 @@ struct Searcher {
                         h0 |= mine[u] && pc(dmask(m0, v[u])) <= d;
                         h1 |= mine[u] && pc(dmask(m1, v[u])) <= d;
                     }
-                    const unsigned long long b0 = ballot(h0);
-                    const unsigned long long b1 = ballot(h1);
-                    if (b0) {
-                        hw[q] |= 1ull << i0;
-                        live--;
-                    }
-                    if (two && b1) {
-                        hw[q] |= 1ull << i1;
-                        live--;
-                    }
+                    const uint64_t b0 = ballot(h0) ? 1ull << i0 : 0ull;
+                    const uint64_t b1 = (two && ballot(h1)) ? 1ull << i1 : 0ull;
+                    hit = uni64(hit | b0 | b1);
                 }
+                hw[q] = uni64(hw[q] | hit);
+                live -= __popcll(hit);
             }
         }
     }
@@ -917,7 +914,7 @@ struct Searcher {
         for (int q = 0; q < kLeafCap / 64; q++) {
             if (q * 64 < nl) {
                 const int nq = nl - q * 64 < 64 ? nl - q * 64 : 64;
-                uint64_t todo = ~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull));
+                uint64_t todo = uni64(~hw[q] & (nq == 64 ? ~0ull : ((1ull << nq) - 1ull)));
                 while (todo) {
                     // the round's l-mers: the G lowest pending ones, one per group
                     const bool set = (todo >> lane) & 1ull;
@@ -931,9 +928,9 @@ struct Searcher {
                     const unsigned long long bm = ballot(act && mine && pc(dmask(m, v)) <= d);
                     const bool hit = sel && ((bm >> (rk * C)) & cmask) != 0ull;
                     const unsigned long long hb = ballot(hit);
-                    hw[q] |= hb;
+                    hw[q] = uni64(hw[q] | hb);
                     live -= __popcll(hb);
-                    todo &= ~ballot(sel);
+                    todo = uni64(todo & ~ballot(sel));
                     __syncthreads();  // S.lix is rewritten by the next round
                 }
             }
