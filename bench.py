@@ -166,7 +166,7 @@ def run_batched(args, I, pms, insts=None):
         insts = I.batch_mix(BATCH_SEED0, args.count)
     probs = [pms.Problem(x.seqs, x.l, x.d, x.alphabet) for x in insts]
     tune = pms.Tune(threshold=args.threshold, waves_per_cu=args.wpc, split=args.split,
-                    stage_cap=args.stage_cap)
+                    stage_cap=args.stage_cap, compat_kernel=args.compat_kernel)
     default_rate = None
     tuned_note = "flags"
     if args.autotune:
@@ -532,6 +532,8 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="part size (0 = auto)")
     ap.add_argument("--threshold", type=int, default=0, help="stack size t (0 = cost model)")
     ap.add_argument("--stage-cap", type=int, default=0, help="staged survivors per tail batch")
+    ap.add_argument("--compat-kernel", type=int, default=0,
+                    help="compat builder: 1 VALU, 2 int8 MFMA (0 = library default)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched: use the flags / defaults instead of pms_autotune")
     ap.add_argument("--tune-runs", type=int, default=24, help="autotuner pipeline runs")

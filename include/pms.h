@@ -96,9 +96,11 @@ typedef struct pms_tune {
     int32_t triple_filter;  /* >= 0: filter survivors with Theorem 1 (default),
                                < 0: pairwise 2d filter only */
     int32_t waves_per_cu;   /* resident search waves per CU (persistent grid); 0 = auto */
-    int32_t compat_kernel;  /* 1: VALU xor/popcount (the only builder in this
-                               version; 2, an int8 one-hot MFMA builder, returns
-                               PMS_E_UNSUPPORTED); 0 = 1 */
+    int32_t compat_kernel;  /* builder of the compat bit-matrix: 1 VALU
+                               xor/popcount; 2 int8 MFMA on one-hot codes
+                               (Hd <= 2d as matches >= l - 2d); 0 = 2 for
+                               alphabets of up to 4 letters, 1 for larger
+                               ones.  Values above 2 are PMS_E_INVAL */
     int32_t split;          /* survivors of the next member's string one wave
                                keeps (1..2047; 0 = 32); the rest are queued in
                                ranges of this size for other waves: at stack

@@ -105,7 +105,7 @@ struct LaunchPlan {
     int words;           // l-mer class: 1, 2 (two 32- / 64-bit planes), 3 (five 32-bit planes)
     int kwords;          // u64 words per motif key (1 or 2)
     int search_blocks;   // persistent grid size
-    int compat_kernel;   // 1 VALU
+    int compat_kernel;   // 1 VALU xor/popcount, 2 int8 one-hot MFMA
     int split;           // survivors of one string a wave keeps (the rest: split items)
     int s2cap;           // staged survivors per tail batch (multiple of 64)
     int deep_phases;     // search launches for deep items (tmax - 3, at least 0)

@@ -233,6 +233,99 @@ __global__ __launch_bounds__(256) void k_compat(const InstDev* __restrict__ inst
     }
 }
 
+// Int8 MFMA builder of the same matrix.  Hd(u, v) <= 2d is matches(u, v) >=
+// l - 2d, and matches(u, v) is the dot product of the one-hot codes of u and
+// v (an l x A vector of 0/1 bytes, A = 4 letters, or the alphabet's size in
+// the five-plane class).  One wave takes 32 rows u and walks every string j
+// and 64-window word w: two 32x32 tiles of v_mfma_i32_32x32x16_i8 over the
+// one-hot K dimension give the 32 x 64 match counts, a ballot per
+// accumulator register turns them into row bits, and each of the first 32
+// lanes writes one row's 64-bit word.
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Bytes k0 .. k0+7 of l-mer x's one-hot code vector (byte k = [code of
+// character k / AL equals k % AL]; 0 beyond the l-mer).
+template <int W>
+__device__ __forceinline__ long onehot8(const Lm<W>& x, int k0, int AL, int l) {
+    uint64_t o = 0;
+    if (AL == 4) {
+        const int p0 = k0 >> 2;  // k0 is a multiple of 8: characters p0, p0 + 1
+        if (p0 < l) o |= 1ull << (8 * code_at(x, p0));
+        if (p0 + 1 < l) o |= 1ull << (32 + 8 * code_at(x, p0 + 1));
+    } else {
+        int p = k0 / AL, c = k0 - p * AL;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (p < l && (int)code_at(x, p) == c) o |= 1ull << (8 * i);
+            if (++c == AL) {
+                c = 0;
+                p++;
+            }
+        }
+    }
+    return (long)o;
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_compat_mfma(const InstDev* __restrict__ insts,
+                                                    const Lm<W>* __restrict__ lmers,
+                                                    uint64_t* __restrict__ compat) {
+    const InstDev I = insts[blockIdx.y];
+    const int N = I.n * I.r;
+    const int Nu = I.c1only ? I.r : N;
+    const int u0 = blockIdx.x * 32;
+    if (N <= 0 || u0 >= Nu) return;
+    const int lane = lane_id();
+    const int AL = W == 3 ? I.asize : 4;
+    const int K = AL * I.l;
+    const int steps = (K + 15) / 16;
+    const int kb = (lane >> 5) * 8;
+    const Lm<W>* L = lmers + I.lmer_off;
+    const int ua = u0 + (lane & 31);  // this lane's row for the A operand
+    const Lm<W> ux = ua < Nu ? L[ua] : lm_zero<W>();
+    const int thr = I.l - 2 * I.d;
+    // the row whose word this lane writes (lanes 0..31): accumulator
+    // register r = (R / 8) * 4 + R % 4 holds it, in the ballot's low half
+    // when (R / 4) is even
+    const int R = lane & 31;
+    const int myr = (R >> 3) * 4 + (R & 3);
+    const bool hi_half = (R >> 2) & 1;
+    const int urow = u0 + R;
+    const int ustr = urow < Nu ? urow / I.r : -1;
+    uint64_t* out = compat + I.compat_off;
+    for (int j = 0; j < I.n; j++) {
+        for (int w = 0; w < I.bw; w++) {
+            const int x0 = w * 64 + (lane & 31), x1 = x0 + 32;
+            const Lm<W> v0 = x0 < I.r ? L[j * I.r + x0] : lm_zero<W>();
+            const Lm<W> v1 = x1 < I.r ? L[j * I.r + x1] : lm_zero<W>();
+            v16i c0 = {0}, c1 = {0};
+            for (int st = 0; st < steps; st++) {
+                const int k0 = st * 16 + kb;
+                const long a = onehot8<W>(ux, k0, AL, I.l);
+                const long b0 = x0 < I.r ? onehot8<W>(v0, k0, AL, I.l) : 0l;
+                const long b1 = x1 < I.r ? onehot8<W>(v1, k0, AL, I.l) : 0l;
+                c0 = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, b0, c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, b1, c1, 0, 0, 0);
+            }
+            uint64_t word = 0;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const uint64_t m0 = ballot(c0[r] >= thr);
+                const uint64_t m1 = ballot(c1[r] >= thr);
+                if (r == myr)
+                    word = hi_half ? ((m0 >> 32) | (m1 & 0xFFFFFFFF00000000ull))
+                                   : ((m0 & 0xFFFFFFFFull) | (m1 << 32));
+            }
+            if (lane < 32 && urow < Nu) {
+                // no bits for the row's own string nor beyond the last window
+                const int left = I.r - w * 64;
+                const uint64_t valid = left >= 64 ? ~0ull : (left > 0 ? (1ull << left) - 1ull : 0ull);
+                out[((int64_t)urow * I.n + j) * I.bw + w] = (j == ustr) ? 0ull : (word & valid);
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------- level-1 expansion
 // One wave per (instance, window u1 of S_1): the level-1 survivors of string j
 // are exactly the compat row C[u1][j] (Algorithm 2's first push and filter).
@@ -2004,6 +2097,19 @@ hipError_t launch_pack(const LaunchPlan& p, const DevBufs& b, hipStream_t stream
 
 hipError_t launch_compat(const LaunchPlan& p, const DevBufs& b, hipStream_t stream) {
     if (p.max_n_lmers <= 0) return hipSuccess;
+    if (p.compat_kernel == 2) {
+        dim3 grid((unsigned)((p.max_n_lmers + 31) / 32), p.n_inst);
+        if (p.words == 1)
+            hipLaunchKernelGGL(k_compat_mfma<1>, grid, dim3(64), 0, stream, b.inst,
+                               (const Lm<1>*)b.lmers, b.compat);
+        else if (p.words == 2)
+            hipLaunchKernelGGL(k_compat_mfma<2>, grid, dim3(64), 0, stream, b.inst,
+                               (const Lm<2>*)b.lmers, b.compat);
+        else
+            hipLaunchKernelGGL(k_compat_mfma<3>, grid, dim3(64), 0, stream, b.inst,
+                               (const Lm<3>*)b.lmers, b.compat);
+        return hipGetLastError();
+    }
     const int ntile = (p.max_n_lmers + kCompatTile - 1) / kCompatTile;
     const long tasks = (long)ntile * p.max_n;
     dim3 grid((unsigned)((tasks + 3) / 4), p.n_inst);

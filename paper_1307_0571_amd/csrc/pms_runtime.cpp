@@ -324,7 +324,11 @@ size_t plan_layout(pms_batch* bt) {
     bt->part_cap = std::max<unsigned long long>(std::min<unsigned long long>(items, 1ull << 22), 1024);
     const int wpc = bt->tune.waves_per_cu > 0 ? bt->tune.waves_per_cu : 20;
     p.search_blocks = device_cus() * wpc;
-    p.compat_kernel = 1;
+    // the MFMA builder where the one-hot vectors are 4 bytes per character
+    // (17.7 vs 27.6 ms on the batched DNA mix); the VALU one for larger
+    // alphabets (32.5 ms vs 382 ms on the protein batch)
+    p.compat_kernel = bt->tune.compat_kernel > 0 ? (int)bt->tune.compat_kernel
+                                                 : (bt->words == 3 ? 1 : 2);
     p.split = bt->tune.split > 0 ? (int)bt->tune.split : kSplitDefault;
     // staged survivors per tail batch (LDS per wave grows with it, so it
     // trades resident waves against checks from HBM): measured on MI355X,
@@ -543,7 +547,7 @@ int make_batch(const pms_instance* inst, int32_t count, const pms_tune* tune, pm
     if (!out || count < 0 || (count > 0 && !inst)) return PMS_E_INVAL;
     if (count > kMaxInst) return PMS_E_UNSUPPORTED;
     if (tune) {
-        if (tune->compat_kernel > 1) return PMS_E_UNSUPPORTED;
+        if (tune->compat_kernel > 2) return PMS_E_INVAL;
         if (tune->split > 2047) return PMS_E_INVAL;
         if (tune->s1_begin < 0 || tune->s1_end < 0 ||
             (tune->s1_end > 0 && tune->s1_begin > tune->s1_end))

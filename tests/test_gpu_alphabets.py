@@ -67,6 +67,15 @@ def test_alphabet_vs_oracle(name, seed, alpha, l, d, n, m):
     assert inst.motif in got
 
 
+@pytest.mark.parametrize("name,seed,alpha,l,d,n,m", [c for c in CASES if c[0] in (
+    "protein_13_5", "protein_8_4_2d_ge_l", "a32_24_9_two_key_words", "a16_32_12_full_width",
+    "binary_34_3_wide", "ternary_10_2", "a8_22_7_word_boundary")])
+def test_alphabet_mfma_compat(name, seed, alpha, l, d, n, m):
+    _say(f"mfma compat {name}")
+    inst = I.planted(seed, l, d, n, m, alphabet=alpha)
+    assert _gpu(inst, pms.Tune(compat_kernel=2)) == _want(inst)
+
+
 def test_packed_keys_layout():
     # pms_solve's packed keys: B-bit codes, floor(64 / B) characters per
     # word, first character in the top bits
@@ -98,6 +107,7 @@ def test_packed_keys_layout():
     dict(threshold=2), dict(threshold=3), dict(threshold=4), dict(threshold=5),
     dict(threshold=5, split=1), dict(triple_filter=-1), dict(compat_mode=2),
     dict(stage_cap=512), dict(waves_per_cu=1), dict(out_capacity=1), dict(split=2),
+    dict(compat_kernel=2), dict(compat_kernel=2, compat_mode=2),
 ])
 def test_protein_invariant_under_tuning(tune):
     _say(f"protein tune {tune}")

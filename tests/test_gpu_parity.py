@@ -75,6 +75,7 @@ def test_plain_gpu_config_seed0(l, d):
     dict(stage_cap=512), dict(stage_cap=4096), dict(threshold=5, stage_cap=512, split=3),
     dict(compat_mode=1), dict(compat_mode=2), dict(compat_mode=2, triple_filter=-1),
     dict(compat_mode=2, threshold=5, split=2), dict(compat_mode=2, threshold=2),
+    dict(compat_kernel=2), dict(compat_kernel=2, compat_mode=2), dict(compat_kernel=2, lmer_words=2),
 ])
 def test_output_invariant_under_tuning(tune):
     _say(f"tune {tune}")
@@ -295,6 +296,21 @@ def test_long_sequences_vs_oracle(name, seed, l, d, n, m, solver, tune):
     got = _gpu(inst, pms.Tune(**tune) if tune else None)
     assert got == want
     assert inst.motif in got
+
+
+# The int8 MFMA compat builder on sizes across tiles and ragged tails, one and
+# two 64-bit planes, 2d >= l (every pair compatible: only the window and
+# own-string masks clear bits), 32 strings and 2048 windows per string.
+@pytest.mark.parametrize("name,seed,l,d,n,m", [
+    ("small_ragged", 4, 9, 2, 10, 257), ("two_words", 11, 33, 8, 5, 120),
+    ("l40", 12, 40, 12, 4, 100), ("2d_ge_l_6_3", 44, 6, 3, 5, 60), ("n32", 41, 9, 2, 32, 400),
+    ("r2048", 43, 9, 1, 3, 2056), ("n1", 10, 6, 2, 1, 40),
+])
+def test_mfma_compat_vs_oracle(name, seed, l, d, n, m):
+    _say(f"mfma compat {name}: seed={seed} l={l} d={d} n={n} m={m}")
+    inst = I.planted(seed, l, d, n, m)
+    want = oracle.solve_a(inst.seqs, l, d) if l <= 12 else oracle.solve_b(inst.seqs, l, d)
+    assert _gpu(inst, pms.Tune(compat_kernel=2)) == want
 
 
 def test_serving_matches_alone():

@@ -165,7 +165,8 @@ def test_tune_validation_is_host_only(lib):
     assert st(s1_begin=-1, s1_end=5) == pms.PMS_E_INVAL
     assert st(split=2048) == pms.PMS_E_INVAL
     assert st(split=1) == pms.PMS_OK
-    assert st(compat_kernel=2) == pms.PMS_E_UNSUPPORTED       # no MFMA builder in this version
+    assert st(compat_kernel=2) == pms.PMS_OK                 # the int8 MFMA builder
+    assert st(compat_kernel=3) == pms.PMS_E_INVAL
     assert st(compat_mode=2) == pms.PMS_OK
     assert st(compat_mode=3) == pms.PMS_E_INVAL
 
