@@ -313,6 +313,18 @@ def test_mfma_compat_vs_oracle(name, seed, l, d, n, m):
     assert _gpu(inst, pms.Tune(compat_kernel=2)) == want
 
 
+# More emitted keys than one LDS sort chunk with two-word keys (l > 32): the
+# multi-block sort (HBM bitonic stages, per-chunk merges, compaction).
+@pytest.mark.parametrize("seed,l,d,n,m", [(61, 34, 6, 2, 34), (63, 33, 6, 2, 34)])
+@pytest.mark.parametrize("ck", [1, 2])
+def test_wide_keys_large_output(seed, l, d, n, m, ck):
+    _say(f"wide keys, large output: seed={seed} l={l} d={d} n={n} m={m} compat_kernel={ck}")
+    inst = I.planted(seed, l, d, n, m)
+    want = oracle.solve_b(inst.seqs, l, d)
+    assert len(want) > 100000
+    assert _gpu(inst, pms.Tune(compat_kernel=ck)) == want
+
+
 def test_serving_matches_alone():
     _say("serving: continuous batching, each result equals the instance alone")
     insts = I.batch_mix(2000, 12, ld=((9, 2), (10, 2), (11, 3)), n_range=(5, 12),
