@@ -332,12 +332,13 @@ size_t plan_layout(pms_batch* bt) {
     p.split = bt->tune.split > 0 ? (int)bt->tune.split : kSplitDefault;
     // staged survivors per tail batch (LDS per wave grows with it, so it
     // trades resident waves against checks from HBM): measured on MI355X,
-    // 1024 suits n*(m-l+1) up to about 12000 l-mers per instance, 512 the
-    // batched mix of larger instances (66.0 instances/s, 64.0 at 256)
+    // 1024 suits n*(m-l+1) up to about 12000 l-mers per instance, 256 the
+    // batched mix of larger instances (with four resident waves per SIMD:
+    // 78.2 instances/s, 73.4 at 512)
     if (bt->tune.stage_cap > 0)
         p.s2cap = std::max(kStageCapMin, std::min(kStageCapMax, (int)(bt->tune.stage_cap + 63) / 64 * 64));
     else
-        p.s2cap = p.max_n_lmers > 12000 ? 512 : 1024;
+        p.s2cap = p.max_n_lmers > 12000 ? 256 : 1024;
     while (p.s2cap > kStageCapMin && search_lds_bytes(p) > (size_t)device_lds_per_block())
         p.s2cap = std::max(kStageCapMin, p.s2cap / 2 / 64 * 64);
     bt->plan_status = search_lds_bytes(p) > (size_t)device_lds_per_block() ? PMS_E_UNSUPPORTED : PMS_OK;
