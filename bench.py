@@ -187,16 +187,19 @@ def run_batched(args, I, pms, insts=None):
             return rate
 
         proposal = pms.autotune(probs, base=base, max_runs=args.tune_runs, sample=64)
-        default_rate = one_pass(base)
-        proposal_rate = one_pass(proposal)
-        if proposal_rate >= default_rate:
-            tune = proposal
-            tuned_note = (f"pms_autotune (64-instance sample); {proposal_rate:.2f} vs "
-                          f"{default_rate:.2f} instances/s with the defaults on the whole batch")
-        else:
-            tune = base
-            tuned_note = (f"defaults: pms_autotune's proposal {pms.tune_dict(proposal)} ran "
-                          f"{proposal_rate:.2f} vs {default_rate:.2f} instances/s on the whole batch")
+        # a sample can favour a threshold the whole batch does not: the
+        # proposal is also timed with the base's threshold
+        kept_t = pms.Tune(**{**pms.tune_dict(proposal), "threshold": base.threshold})
+        cands = [("defaults", base), ("proposal", proposal)]
+        if proposal.threshold != base.threshold:
+            cands.append(("proposal with the default threshold", kept_t))
+        rates = [(one_pass(t), name, t) for name, t in cands]
+        default_rate = rates[0][0]
+        best = max(rates, key=lambda x: x[0])
+        tune = best[2]
+        tuned_note = (f"{best[1]} of pms_autotune (64-instance sample) on the whole batch: " +
+                      ", ".join(f"{name} {r:.2f}" for r, name, _ in rates) + " instances/s; proposal " +
+                      json.dumps({k: v for k, v in pms.tune_dict(proposal).items() if v}))
     b = pms.Batch(probs, tune=tune)
     for _ in range(args.warmup):
         b.run()
