@@ -131,10 +131,10 @@ typedef struct pms_tune {
 } pms_tune;
 
 /* Autotuner.  Times the device pipeline on an evenly spread sample of at
- * most `sample` of the instances (0 = 32) for candidate settings -- the
- * threshold t first (which Section 2.2 and Appendix D leave to
- * measurement), then staged survivors per tail batch, part size, waves per
- * CU, the Theorem 1 filter, the l-mer width -- one parameter at a time from
+ * most `sample` of the instances (0 = 32) for candidate settings -- staged
+ * survivors per tail batch, part size, waves per CU, the threshold t (which
+ * Section 2.2 and Appendix D leave to measurement), the Theorem 1 filter,
+ * the l-mer width -- one parameter at a time from
  * `base` (NULL = the defaults), at most max_runs pipeline runs (0 = 16),
  * keeping a change only when it is at least 2% faster on the sample, and
  * writes the best setting to out (a sample can mislead: time the proposal

@@ -2,9 +2,9 @@
 //
 // Every setting of pms_tune except the S_1 window range gives the same motif
 // sets, so the fastest one can be chosen by measurement, in this order: the
-// threshold t (Section 2.2 and Appendix D leave it to be set empirically),
-// the staged survivors per tail batch (LDS per wave, hence resident waves),
-// the part size, the persistent waves per CU, the Theorem 1 survivor filter
+// staged survivors per tail batch (LDS per wave, hence resident waves), the
+// part size, the persistent waves per CU, the threshold t (Section 2.2 and
+// Appendix D leave it to be set empirically), the Theorem 1 survivor filter
 // and the l-mer width.  The tuner times the whole device pipeline on a sample of the
 // caller's instances and walks the parameters one at a time (coordinate
 // descent from the library's defaults), keeping a change only when it is at
@@ -175,13 +175,15 @@ extern "C" int pms_autotune(const pms_instance* inst, int32_t count, const pms_t
         int32_t pms_tune::*field;
         std::vector<int32_t> values;
     };
-    // the threshold first: it changes the work itself (a stack of 4 instead
-    // of 3 is 30% faster on protein batches and 4x slower on the DNA mix)
+    // the threshold after the launch parameters: it changes the work itself
+    // (a stack of 4 instead of 3 is 30% faster on protein batches and 4x
+    // slower on the DNA mix), and taken first from a sample it can lock the
+    // descent into a stack size the whole batch does not favour
     const std::vector<Dim> dims = {
-        {&pms_tune::threshold, {3, 4, 2}},
         {&pms_tune::stage_cap, {256, 384, 512, 768, 1024, 2048}},
         {&pms_tune::split, {16, 24, 48, 64}},
         {&pms_tune::waves_per_cu, {8, 12, 16, 24}},
+        {&pms_tune::threshold, {3, 4, 2}},
         {&pms_tune::triple_filter, {-1}},
         {&pms_tune::lmer_words, {2}},
     };
