@@ -228,6 +228,14 @@ def run_batched(args, I, pms, insts=None):
         if rg != res:
             raise SystemExit("graph replay result differs from the eager run")
     b.close()
+    # the same batch from host buffers: validation, encoding, upload, the
+    # pipeline and the copy back (pms_solve_batch), PCIe included
+    pms.solve_batch(probs, tune=tune)
+    th = time.perf_counter()
+    hres = pms.solve_batch(probs, tune=tune)
+    host_rate = len(probs) / (time.perf_counter() - th)
+    if hres != res:
+        raise SystemExit("host-buffer result differs from the resident run")
     plain = None
     if not args.no_plain:
         singles = [pms.Batch([p]) for p in probs]  # pms_solve's own setting
@@ -243,12 +251,13 @@ def run_batched(args, I, pms, insts=None):
         plain = time.perf_counter() - tp
         for sb in singles:
             sb.close()
-    return insts, elapsed, phases, plain, graph_rate, [len(r) for r in res], tune, default_rate, tuned_note
+    return (insts, elapsed, phases, plain, graph_rate, [len(r) for r in res], tune, default_rate,
+            tuned_note, host_rate)
 
 
 def batched_main(args, I, pms):
-    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note = run_batched(
-        args, I, pms)
+    (insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note,
+     host_rate) = run_batched(args, I, pms)
     n = len(insts)
     value = n * args.steps / elapsed
     t_of = [tune.threshold or pms.default_threshold(x.n, x.m, x.l, x.d) for x in insts]
@@ -302,6 +311,7 @@ def batched_main(args, I, pms):
         "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
         "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
         "graph_instances_per_s": round(graph_rate, 3) if graph_rate else None,
+        "host_buffers_instances_per_s": round(host_rate, 3),
         "hd_compares_per_s": {
             "compat": round(compat / (ms_step * 1e-3), 1),
             "compat_phase": round(compat / (compat_ms * 1e-3), 1),
@@ -322,8 +332,8 @@ def protein_main(args, I, pms):
     """The batched configuration over the 20 amino acids (five-plane l-mers,
     5-bit keys): batched and plain rates and the CPU oracle beside them."""
     insts = I.batch_mix(PROTEIN_SEED0, args.count, ld=PROTEIN_LD, alphabet=I.PROTEIN)
-    insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note = run_batched(
-        args, I, pms, insts)
+    (insts, elapsed, phases, plain_s, graph_rate, sizes, tune, default_rate, tuned_note,
+     host_rate) = run_batched(args, I, pms, insts)
     n = len(insts)
     value = n * args.steps / elapsed
     out = {"workload": f"protein batched: {n} planted instances over the 20 amino acids, (l,d) "
@@ -336,6 +346,7 @@ def protein_main(args, I, pms):
            "plain_instances_per_s": round(n / plain_s, 3) if plain_s else None,
            "batched_over_plain": round(value / (n / plain_s), 3) if plain_s else None,
            "graph_instances_per_s": round(graph_rate, 3) if graph_rate else None,
+           "host_buffers_instances_per_s": round(host_rate, 3),
            "phases_ms": {k: round(sum(p[i] for p in phases) / len(phases), 3)
                          for i, k in enumerate(("pack", "compat", "expand", "search", "sort"))},
            "max_motifs_per_instance": max(sizes)}
