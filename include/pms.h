@@ -102,7 +102,8 @@ typedef struct pms_tune {
                                alphabets of up to 4 letters, 1 for larger
                                ones.  Values above 2 are PMS_E_INVAL */
     int32_t split;          /* survivors of the next member's string one wave
-                               keeps (1..2047; 0 = 32); the rest are queued in
+                               keeps (1..2047; 0 = 32, or 64 when an instance
+                               has more than 12000 l-mers); the rest are queued in
                                ranges of this size for other waves: at stack
                                size 2 as part items (a second launch), at 3
                                and up as deep items (further launches) */

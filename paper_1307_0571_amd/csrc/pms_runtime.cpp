@@ -329,7 +329,10 @@ size_t plan_layout(pms_batch* bt) {
     // alphabets (32.5 ms vs 382 ms on the protein batch)
     p.compat_kernel = bt->tune.compat_kernel > 0 ? (int)bt->tune.compat_kernel
                                                  : (bt->words == 3 ? 1 : 2);
-    p.split = bt->tune.split > 0 ? (int)bt->tune.split : kSplitDefault;
+    // part size: 32 for instances up to about 12000 l-mers (the plain
+    // n = 20, m = 600 ones), 64 for larger ones (the batched mix: 80 vs 68
+    // instances/s, the autotuner's choice there)
+    p.split = bt->tune.split > 0 ? (int)bt->tune.split : (p.max_n_lmers > 12000 ? 64 : kSplitDefault);
     // staged survivors per tail batch (LDS per wave grows with it, so it
     // trades resident waves against checks from HBM): measured on MI355X,
     // 1024 suits n*(m-l+1) up to about 12000 l-mers per instance, 256 the
