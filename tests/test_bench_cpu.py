@@ -22,3 +22,20 @@ def test_lane_op_model_counts_every_unit():
     # per node at t = 3: 4 * (3 pairs + 1 triple); at t = 4: 4 * (6 + 4)
     assert bench.lane_ops(u, 3) == 2 * 7 + 14 * 10 + 16 * 100 + 5 * 1000
     assert bench.lane_ops(u, 4) == 2 * 7 + 14 * 10 + 40 * 100 + 5 * 1000
+
+
+def test_traffic_record_is_consistent():
+    # HBM bytes per launch = FETCH_SIZE and WRITE_SIZE (KiB per dispatch pair)
+    # scaled by what the same counters read for a copy of known size
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    cal = t["copy_calibration"]
+    assert abs(cal["fetch_factor"] - cal["bytes"] / (cal["fetch_size_kib"] * 1024)) < 1e-9
+    assert abs(cal["write_factor"] - cal["bytes"] / (cal["write_size_kib"] * 1024)) < 1e-9
+    assert abs(t["fetch_bytes"] - t["fetch_size_kib"] * 1024 * cal["fetch_factor"]) < 1e3
+    assert abs(t["write_bytes"] - t["write_size_kib"] * 1024 * cal["write_factor"]) < 1e3
+    assert t["hbm_bytes_per_launch"] == t["fetch_bytes"] + t["write_bytes"]
+    # the record only counts while the kernel and launch sources are the ones measured
+    assert (bench.load_traffic() is not None) == (t["kernel_source_sha256"] == bench.kernel_sha256())
