@@ -433,6 +433,41 @@ def large_main(args, I, pms):
     print(json.dumps(out), flush=True)
 
 
+def long_main(args, I, pms):
+    """Long strings (up to 8192 windows each): every instance runs with the
+    library's choice of compat layout (the whole matrix below 1 GiB, else
+    S_1's rows only) and with S_1's rows forced; both must give the same set,
+    holding the planted motif.  One warm-up run per layout, then one timed."""
+    out = {"workload": "long strings: planted DNA, n 6-20, 4000-8203 characters"}
+    cases = ((50, 12, 2, 6, 8203), (47, 9, 1, 12, 8200), (60, 15, 4, 20, 4000),
+             (61, 16, 4, 20, 8000), (62, 17, 5, 20, 4000))
+    for (seed, l, d, n, m) in cases:
+        inst = I.planted(seed, l, d, n, m)
+        name = f"({l},{d}) n={n} m={m} seed {seed}"
+        row, sets = {}, []
+        for mode, label in ((0, "auto"), (2, "s1_rows")):
+            b = pms.Batch([pms.Problem(inst.seqs, l, d)], tune=pms.Tune(compat_mode=mode))
+            b.run()
+            b.results()
+            t0 = time.perf_counter()
+            b.run()
+            res = b.results()[0]
+            dt = time.perf_counter() - t0
+            ph = b.timings()
+            b.close()
+            if inst.motif not in res:
+                raise SystemExit(f"planted motif missing for {name} ({label})")
+            sets.append(res)
+            row[label] = {"s": round(dt, 4), "compat_ms": round(ph[1], 3),
+                          "search_ms": round(ph[3], 3), "motifs": len(res)}
+        if sets[0] != sets[1]:
+            raise SystemExit(f"the two compat layouts disagree on {name}")
+        row["compat_matrix_bytes"] = (n * (m - l + 1)) * n * ((m - l + 64) // 64) * 8
+        out[name] = row
+        print(json.dumps({name: row}), flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def serving_main(args, I, pms):
     """A Poisson stream of planted instances with (l,d) uniform from
     {(9,2),(11,3),(13,4),(15,5),(17,6)}, n in [10,30], m in [200,1000].  The
@@ -533,7 +568,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["batched", "plain", "serving", "large", "protein"],
+    ap.add_argument("--workload", choices=["batched", "plain", "serving", "large", "protein",
+                                           "long"],
                     default="batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -564,7 +600,7 @@ def main():
     from paper_1307_0571_amd import instances as I
     from paper_1307_0571_amd import pms
     {"batched": batched_main, "plain": plain_main, "serving": serving_main,
-     "large": large_main, "protein": protein_main}[args.workload](args, I, pms)
+     "large": large_main, "protein": protein_main, "long": long_main}[args.workload](args, I, pms)
 
 
 if __name__ == "__main__":
