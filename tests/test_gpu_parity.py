@@ -298,6 +298,28 @@ def test_long_sequences_vs_oracle(name, seed, l, d, n, m, solver, tune):
     assert inst.motif in got
 
 
+# Long strings at the paper's n = 20, on 24 S_1 windows around the planted
+# copy (the oracle builds the whole matrix, about 17 s on one core): (16,4)
+# at m = 5000, whose whole matrix (1.24 GB) makes the library take S_1's
+# rows by itself, and (15,4) at m = 4000 with the whole matrix (0.8 GB) and
+# with S_1's rows forced.
+@pytest.mark.parametrize("seed,l,d,m,tunes", [
+    (61, 16, 4, 5000, (None,)),
+    (60, 15, 4, 4000, (None, dict(compat_mode=2))),
+])
+def test_long_strings_n20_windows_vs_oracle(seed, l, d, m, tunes):
+    inst = I.planted(seed, l, d, 20, m)
+    a = max(0, inst.starts[0] - 12)
+    b = a + 24
+    _say(f"long n=20: seed={seed} l={l} d={d} m={m} S1 windows [{a},{b})")
+    want = oracle.solve_b(inst.seqs, l, d, windows=(a, b))
+    assert inst.motif in want
+    for tune in tunes:
+        _say(f"  tune {tune}")
+        got = _gpu(inst, pms.Tune(s1_begin=a, s1_end=b, **(tune or {})))
+        assert got == want
+
+
 # The int8 MFMA compat builder on sizes across tiles and ragged tails, one and
 # two 64-bit planes, 2d >= l (every pair compatible: only the window and
 # own-string masks clear bits), 32 strings and 2048 windows per string.
