@@ -179,3 +179,20 @@ def test_autotune_argument_checks(lib):
     assert out.split == 7
     assert lib.pms_autotune(None, 1, None, 4, 4, ctypes.byref(out)) == pms.PMS_E_INVAL
     assert lib.pms_autotune(None, 0, None, 4, 4, None) == pms.PMS_E_INVAL
+
+
+def test_compat_layout_choice_is_host_only(lib):
+    # the whole matrix while it stays under 1 GiB, S_1's rows above (section
+    # 2.2's memory bound): n = 20 at 4000 characters keeps the whole 0.8 GB
+    # matrix, at 5000 characters (1.24 GB) only S_1's rows, as if forced
+    def ws(m, mode):
+        inst = I.planted(61, 16, 4, 20, m)
+        mar = pms._Marshal([pms.Problem(inst.seqs, 16, 4)])
+        sz = ctypes.c_size_t(0)
+        t = pms.Tune(compat_mode=mode)
+        assert lib.pms_batch_workspace_size(mar.arr, 1, ctypes.byref(t), ctypes.byref(sz)) == pms.PMS_OK
+        return sz.value
+    whole = (20 * 3985) * 20 * ((3985 + 63) // 64) * 8
+    assert ws(4000, 0) == ws(4000, 1) >= whole
+    assert ws(4000, 2) < ws(4000, 0) - whole // 2
+    assert ws(5000, 0) == ws(5000, 2) < ws(5000, 1)
