@@ -196,3 +196,19 @@ def test_compat_layout_choice_is_host_only(lib):
     assert ws(4000, 0) == ws(4000, 1) >= whole
     assert ws(4000, 2) < ws(4000, 0) - whole // 2
     assert ws(5000, 0) == ws(5000, 2) < ws(5000, 1)
+
+
+def test_expected_motifs_matches_oracle_means(lib):
+    # Appendix C: over i.i.d. uniform strings the expected number of l-mers
+    # within d of some window of every string; the mean of the oracle's set
+    # sizes over 200 seeds must agree within 4 standard errors plus 3% (the
+    # expectation treats overlapping windows as independent)
+    import statistics
+    import oracle
+    for (n, m, l, d, alpha) in [(4, 40, 6, 1, "ACGT"), (5, 60, 7, 2, "ACGT"), (3, 30, 5, 1, "ACG"),
+                                (4, 50, 8, 2, "01"), (3, 40, 4, 1, I.PROTEIN)]:
+        cs = [len(oracle.solve_a(I.random_strings(s, n, m, alpha).seqs, l, d, alphabet=alpha))
+              for s in range(200)]
+        mean, se = statistics.mean(cs), statistics.stdev(cs) / len(cs) ** 0.5
+        e = pms.expected_motifs(n, m, l, d, len(alpha))
+        assert abs(mean - e) <= 4 * se + 0.03 * e, (n, m, l, d, len(alpha), mean, se, e)
